@@ -1,0 +1,150 @@
+/*
+ * simproj.h -- exact projection of a piecewise-linear density defined on a
+ * simplicial mesh onto a regular grid, on AMD Instinct MI355X (gfx950).
+ *
+ * Operation (Sousbie & Colombi, "ColDICE", Section 3.1, eq. eq_firstOrder and
+ * the input/output statement of the exact-projection algorithm, Appendix D):
+ * for every grid cell G_j
+ *
+ *     P_j = sum over simplices S_i of  integral over (S_i intersect G_j) of rho_i(x) dx,
+ *
+ * where rho_i is the linear interpolant of simplex i's D+1 vertex densities
+ * (per vertex, or per corner with SP_RHO_PER_CORNER).  The output is the
+ * density P_j / |G_j| (default) or the mass P_j (SP_OUT_MASS).  Simplices of
+ * either orientation are accepted: each contributes rho integrated over the
+ * region it covers.  Overlapping simplices (a multi-stream sheet) add up.
+ *
+ * Conventions.
+ *   - Cell j = (i, j, k) covers [origin + i h, origin + (i+1) h) per axis,
+ *     h = extent / dims; the output grid is C order [dims2][dims1][dims0]
+ *     (x fastest), 2D [dims1][dims0].
+ *   - Periodic axes: each simplex is unwrapped to the minimum image of its
+ *     first vertex; its extent must be < extent/2 along that axis.
+ *     Contributions on non-periodic axes outside [0, dims) are dropped.
+ *   - A point exactly on a cell face belongs to the upper cell.  This only
+ *     decides measure-zero sets; integrals do not depend on it.
+ *   - Zero-volume simplices deposit nothing and are not errors.
+ *
+ * Precision.
+ *   SP_PREC_FP64   positions, densities and output in double; clipping,
+ *                  integration and accumulation in double.
+ *   SP_PREC_FP32C  positions, densities and output in float; clipping and
+ *                  integration in float on error-free cell-local
+ *                  coordinates, per-cell compensated (hi, lo) accumulation;
+ *                  double only for the orientation of near-degenerate
+ *                  simplices and for the total-mass reduction.
+ *
+ * Memory and streams.  Every data pointer in sp_problem is a DEVICE pointer
+ * owned by the caller; the buffers must stay valid until the work enqueued
+ * on `stream` (a hipStream_t, NULL for the default stream) has completed.
+ * All projection calls are asynchronous: they validate their arguments on
+ * the host, enqueue kernels and return.  On the device every simplex is
+ * checked before it is cut: one with a vertex index outside [0, n_vert), a
+ * non-finite position or density, or an extent of half the box or more on a
+ * periodic axis (32768 cells on another) is skipped; with SP_VALIDATE the
+ * first such error is reported by sp_sync_status.  The context owns its
+ * scratch memory; a context must not be used by two host threads at once,
+ * and calls on one context must be ordered (one stream, or synchronised).
+ */
+#ifndef SIMPROJ_H
+#define SIMPROJ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sp_ctx sp_ctx;
+
+typedef enum {
+    SP_OK = 0,
+    SP_E_INVALID_ARG = 1,   /* null pointer, bad dims/sizes, unsupported flag */
+    SP_E_OUT_OF_RANGE = 2,  /* (SP_VALIDATE) a vertex index outside [0, n_vert) */
+    SP_E_NONFINITE = 3,     /* (SP_VALIDATE) a NaN/Inf position or density */
+    SP_E_PERIODIC_SPAN = 4, /* (SP_VALIDATE) a simplex spans >= extent/2 on a periodic axis */
+    SP_E_NO_MEMORY = 5,     /* scratch allocation failed */
+    SP_E_DEVICE = 6,        /* no usable HIP device, or a HIP call failed */
+    SP_E_UNSUPPORTED = 7,   /* valid request this build does not handle */
+    SP_E_INTERNAL = 8       /* a polytope exceeded every capacity (should not happen) */
+} sp_status;
+
+typedef enum { SP_PREC_FP64 = 0, SP_PREC_FP32C = 1 } sp_precision;
+
+enum {
+    SP_PERIODIC_X = 1u,
+    SP_PERIODIC_Y = 2u,
+    SP_PERIODIC_Z = 4u,
+    SP_RHO_PER_CORNER = 8u, /* rho is [n_simplex][D+1] instead of [n_vert]          */
+    SP_OUT_MASS = 16u,      /* write mass per cell instead of density                 */
+    SP_ACCUMULATE = 32u,    /* add into out (and out_lo) instead of overwriting them  */
+    SP_VALIDATE = 64u       /* report skipped (invalid) simplices via sp_sync_status  */
+};
+
+/* Grid: cell (i,j,k) covers origin + [i,i+1)*h ... with h = extent/dims.
+ * 2D problems use entries [0] and [1] only. */
+typedef struct {
+    double origin[3];
+    double extent[3];
+    int32_t dims[3];
+    uint32_t flags;
+} sp_grid;
+
+typedef struct {
+    const void *xyz;           /* [n_vert][D], double (FP64) or float (FP32C)              */
+    int64_t n_vert;            /* 0 <= n_vert < 2^31                                        */
+    const int32_t *simplices;  /* [n_simplex][D+1] vertex indices                           */
+    int64_t n_simplex;         /* 0 <= n_simplex < 2^31                                     */
+    const void *rho;           /* [n_vert], or [n_simplex][D+1] with SP_RHO_PER_CORNER      */
+    sp_grid grid;
+    void *out;                 /* grid, double (FP64) or float (FP32C)                      */
+    float *out_lo;             /* FP32C only, optional: low part of the compensated sum;
+                                  when given, out holds the high part and out + out_lo is
+                                  the result; when NULL, out receives the rounded sum      */
+    double *total_mass;        /* optional device double, overwritten with the FP64 sum
+                                  over all cells of the output grid, in mass units        */
+} sp_problem;
+
+/* Create a context on HIP device `hip_device`.  SP_E_DEVICE when the device
+ * does not exist or is not gfx950.  *ctx is NULL on failure. */
+sp_status sp_create(int hip_device, sp_ctx **ctx);
+
+/* Release the context and its scratch memory (waits for its device to be
+ * idle first).  NULL is accepted. */
+void sp_destroy(sp_ctx *ctx);
+
+/* Project tetrahedra (D = 3).  Section 3, eq. eq_firstOrder; the hot path of
+ * Appendix D's algorithm (the per-simplex single-voxel shortcut of its first
+ * step included).  Host-detectable argument errors return synchronously and
+ * enqueue nothing. */
+sp_status sp_project_tets(sp_ctx *ctx, const sp_problem *prob, sp_precision prec, void *stream);
+
+/* Project triangles (D = 2): the same operation in two dimensions (the
+ * paper's 2D, i.e. 4D phase-space, case; Section 3.1 eq. eq:E02D). */
+sp_status sp_project_tris(sp_ctx *ctx, const sp_problem *prob, sp_precision prec, void *stream);
+
+/* Project n independent problems of dimension `dim` (3 only in this build)
+ * in one persistent, work-stealing launch; `probs` is a HOST array of n
+ * problems whose buffers are device pointers.  Equivalent to n calls of
+ * sp_project_tets, with the load balanced across all of them (the
+ * cost-based balancing the paper proposes in Section 7). */
+sp_status sp_project_batch(sp_ctx *ctx, int dim, const sp_problem *probs, int n, sp_precision prec, void *stream);
+
+/* Wait for `stream`, then report the first device-side error recorded since
+ * the previous call (SP_VALIDATE checks, capacity failures) and clear it. */
+sp_status sp_sync_status(sp_ctx *ctx, void *stream);
+
+/* Time the tunable launch parameters on the given sample problems and keep
+ * the fastest for subsequent calls; when cache_path is not NULL, read the
+ * result from that file if present, else write it there.  Synchronous. */
+sp_status sp_autotune(sp_ctx *ctx, int dim, const sp_problem *sample, int n, sp_precision prec,
+                      const char *cache_path);
+
+/* Message describing the last error returned on this thread. */
+const char *sp_last_error(const sp_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SIMPROJ_H */

@@ -1,0 +1,769 @@
+// simproj.hip -- MI355X (gfx950) kernels and C-ABI runtime for the exact
+// projection of a piecewise-linear density on a simplicial mesh onto a
+// regular grid (Section 3.1, eq. eq_firstOrder).
+//
+// Path of one call (sp_project_tets / sp_project_tris):
+//   k_fill      zero the output (unless SP_ACCUMULATE) and the per-call state
+//   k_setup     per simplex: gather, unwrap, cell coordinates, orientation;
+//               a simplex inside one cell deposits its whole mass at once
+//               (Appendix D, first step); the others are binned into cost
+//               classes, big ones split into groups of x-slabs
+//   k_scan      class offsets, most expensive class first
+//   k_scatter   the work items in class order
+//   k_clip      persistent waves pull 64 items at a time; each lane sweeps
+//               its simplex through slabs, columns and cells, clipping a
+//               polytope held in LDS and depositing each piece
+//   k_clip(big) items whose polytope overflowed, resumed with more room
+//   k_finalize  hi+lo -> out, FP64 total mass
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <chrono>
+#include <string>
+#include <vector>
+
+#include "simproj.h"
+#include "sp_setup.h"
+
+using namespace sp;
+
+namespace {
+
+constexpr int WG = 64;       // lanes per block in the clip kernels (one wave)
+constexpr int NCLS = 16;     // cost classes
+constexpr int MAXV3 = 24;    // polytope vertex slots per lane (measured peak 22)
+constexpr int MAXV3_BIG = 32;
+constexpr int MAXP2 = 12;    // polygon vertices per lane and buffer (peak 8)
+constexpr int OVF_CAP = 1 << 16;
+
+// Per-call device state, cleared at the start of every call.
+struct CallState {
+    unsigned hist[NCLS];
+    unsigned cursor[NCLS];
+    unsigned total;
+    unsigned head;
+    unsigned extra;
+    unsigned ovf_count;
+    unsigned ovf_head;
+};
+
+// Error state, kept until sp_sync_status reads and clears it.
+struct ErrState {
+    int first;
+    int n_bad_index;
+    int n_nonfinite;
+    int n_bad_span;
+    int n_overflow;
+    int n_internal;
+};
+
+struct Ovf {
+    int s, ix, iy, iz, end;
+};
+
+struct Tuning {
+    int slab_group;   // x-slabs per work item for big simplices
+    int chunks_per_cu; // persistent blocks per CU in the clip kernel (0: occupancy)
+};
+
+__device__ inline void record_error(ErrState *e, int code)
+{
+    atomicCAS(&e->first, 0, code);
+}
+
+// ---------------------------------------------------------------------------
+// deposits
+
+// Compensated FP32 deposit: the returning atomic gives the value the add was
+// applied to; TwoSum recovers its exact rounding error, which goes to the
+// low grid, so hi + lo keeps the exact sum up to the rounding of the low
+// parts (Knuth's TwoSum; requires round-to-nearest atomics).
+struct DepF32 {
+    float *hi;
+    float *lo;
+    int anchor[3];
+    int dims[3];
+    int periodic[3];
+    float scale;
+    int suppress_iy, suppress_iz, suppress_ix;  // resume: skip pieces before this one
+
+    __device__ void operator()(int ix, int iy, int iz, float v)
+    {
+        if (ix == suppress_ix && (iy < suppress_iy || (iy == suppress_iy && iz < suppress_iz))) return;
+        int c[3] = {anchor[0] + ix, anchor[1] + iy, anchor[2] + iz};
+        for (int d = 0; d < 3; ++d) {
+            if (periodic[d]) {
+                c[d] %= dims[d];
+                if (c[d] < 0) c[d] += dims[d];
+            } else if (c[d] < 0 || c[d] >= dims[d]) {
+                return;
+            }
+        }
+        size_t idx = (size_t)c[0] + (size_t)dims[0] * ((size_t)c[1] + (size_t)dims[1] * (size_t)c[2]);
+        float x = v * scale;
+        float old = unsafeAtomicAdd(hi + idx, x);
+        float s = old + x;
+        float bb = s - old;
+        float err = (old - (s - bb)) + (x - bb);
+        if (err != 0.0f) unsafeAtomicAdd(lo + idx, err);
+    }
+};
+
+struct DepF64 {
+    double *out;
+    int anchor[3];
+    int dims[3];
+    int periodic[3];
+    double scale;
+    int suppress_iy, suppress_iz, suppress_ix;
+
+    __device__ void operator()(int ix, int iy, int iz, double v)
+    {
+        if (ix == suppress_ix && (iy < suppress_iy || (iy == suppress_iy && iz < suppress_iz))) return;
+        int c[3] = {anchor[0] + ix, anchor[1] + iy, anchor[2] + iz};
+        for (int d = 0; d < 3; ++d) {
+            if (periodic[d]) {
+                c[d] %= dims[d];
+                if (c[d] < 0) c[d] += dims[d];
+            } else if (c[d] < 0 || c[d] >= dims[d]) {
+                return;
+            }
+        }
+        size_t idx = (size_t)c[0] + (size_t)dims[0] * ((size_t)c[1] + (size_t)dims[1] * (size_t)c[2]);
+        unsafeAtomicAdd(out + idx, v * scale);
+    }
+};
+
+template <typename T>
+struct DepFor;
+template <>
+struct DepFor<float> {
+    using type = DepF32;
+};
+template <>
+struct DepFor<double> {
+    using type = DepF64;
+};
+
+// ---------------------------------------------------------------------------
+// problem description as the kernels see it
+
+template <typename T>
+struct ProbDev {
+    const T *xyz;
+    int64_t n_vert;
+    const int32_t *simp;
+    int64_t n;
+    const T *rho;
+    int per_corner;
+    int validate;
+    GridDev g;
+    T *out;        // hi (FP32C) or the grid (FP64)
+    float *lo;     // FP32C low grid
+    uint32_t *tinfo;
+    uint64_t *items;
+    unsigned extra_cap;
+    Ovf *ovf;
+    CallState *cs;
+    ErrState *es;
+    int slab_group;
+};
+
+template <int D>
+__device__ inline int setup_any(const ProbDev<float> &p, int64_t s, bool validate, Local<float> &L)
+{
+    return setup_f32<D>(p.xyz, p.n_vert, p.simp, s, p.rho, p.per_corner != 0, p.g, validate, L);
+}
+template <int D>
+__device__ inline int setup_any(const ProbDev<double> &p, int64_t s, bool validate, Local<double> &L)
+{
+    return setup_f64<D>(p.xyz, p.n_vert, p.simp, s, p.rho, p.per_corner != 0, p.g, validate, L);
+}
+
+template <typename T>
+__device__ inline typename DepFor<T>::type make_dep(const ProbDev<T> &p, const Local<T> &L);
+template <>
+__device__ inline DepF32 make_dep<float>(const ProbDev<float> &p, const Local<float> &L)
+{
+    DepF32 d;
+    d.hi = p.out;
+    d.lo = p.lo;
+    for (int k = 0; k < 3; ++k) {
+        d.anchor[k] = L.anchor[k];
+        d.dims[k] = p.g.dims[k];
+        d.periodic[k] = p.g.periodic[k];
+    }
+    d.scale = (float)p.g.out_scale;
+    d.suppress_ix = -1;
+    d.suppress_iy = 0;
+    d.suppress_iz = 0;
+    return d;
+}
+template <>
+__device__ inline DepF64 make_dep<double>(const ProbDev<double> &p, const Local<double> &L)
+{
+    DepF64 d;
+    d.out = p.out;
+    for (int k = 0; k < 3; ++k) {
+        d.anchor[k] = L.anchor[k];
+        d.dims[k] = p.g.dims[k];
+        d.periodic[k] = p.g.periodic[k];
+    }
+    d.scale = p.g.out_scale;
+    d.suppress_ix = -1;
+    d.suppress_iy = 0;
+    d.suppress_iz = 0;
+    return d;
+}
+
+// Expected number of pieces of a simplex with this local geometry: the
+// volume of its Minkowski sum with a unit cell (volume + projected areas +
+// widths + 1 in 3D; area + widths + 1 in 2D), a cost proxy for binning.
+template <typename T, int D>
+__device__ inline float piece_estimate(const Local<T> &L)
+{
+    float w[3];
+    for (int d = 0; d < 3; ++d) {
+        float mn = 1e30f, mx = -1e30f;
+        for (int a = 0; a <= D; ++a) {
+            float c = (float)(d == 0 ? L.v[a].x : (d == 1 ? L.v[a].y : L.v[a].z));
+            mn = fminf(mn, c);
+            mx = fmaxf(mx, c);
+        }
+        w[d] = mx - mn;
+    }
+    if (D == 2) return (float)L.det * 0.5f + w[0] + w[1] + 1.0f;
+    float area[3] = {0.f, 0.f, 0.f};
+    for (int k = 0; k < 4; ++k) {
+        int i0 = (k + 1) & 3, i1 = (k + 2) & 3, i2 = (k + 3) & 3;
+        float ax = (float)(L.v[i1].x - L.v[i0].x), ay = (float)(L.v[i1].y - L.v[i0].y), az = (float)(L.v[i1].z - L.v[i0].z);
+        float bx = (float)(L.v[i2].x - L.v[i0].x), by = (float)(L.v[i2].y - L.v[i0].y), bz = (float)(L.v[i2].z - L.v[i0].z);
+        area[0] += fabsf(ay * bz - az * by);
+        area[1] += fabsf(az * bx - ax * bz);
+        area[2] += fabsf(ax * by - ay * bx);
+    }
+    return (float)L.det / 6.0f + 0.25f * (area[0] + area[1] + area[2]) + w[0] + w[1] + w[2] + 1.0f;
+}
+
+// ---------------------------------------------------------------------------
+// kernels
+
+template <typename T>
+__global__ void k_fill(T *p, size_t n)
+{
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t st = (size_t)gridDim.x * blockDim.x;
+    for (; i < n; i += st) p[i] = T(0);
+}
+
+__global__ void k_clear_state(CallState *cs, double *total)
+{
+    unsigned *w = reinterpret_cast<unsigned *>(cs);
+    for (int i = threadIdx.x; i < (int)(sizeof(CallState) / 4); i += blockDim.x) w[i] = 0u;
+    if (threadIdx.x == 0 && total) *total = 0.0;
+}
+
+template <int D, typename T>
+__global__ __launch_bounds__(256) void k_setup(ProbDev<T> p)
+{
+    __shared__ unsigned s_hist[NCLS];
+    if (threadIdx.x < NCLS) s_hist[threadIdx.x] = 0u;
+    __syncthreads();
+    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < p.n) {
+        Local<T> L;
+        int st = setup_any<D>(p, s, p.validate != 0, L);
+        uint32_t info = 0u;
+        if (st == SETUP_OK) {
+            if (L.span[0] == 1 && L.span[1] == 1 && L.span[2] == 1) {
+                // the whole simplex lies in one cell: deposit its mass
+                T rs = L.v[0].r + L.v[1].r + L.v[2].r + (D == 3 ? L.v[3].r : T(0));
+                T val = D == 3 ? L.det * rs / T(24) : L.det * rs / T(6);
+                auto dep = make_dep<T>(p, L);
+                dep(0, 0, 0, val);
+            } else {
+                int sx = L.span[0];
+                int G = p.slab_group;
+                int nit = (sx + G - 1) / G;
+                if (nit > 1) {
+                    unsigned old = atomicAdd(&p.cs->extra, (unsigned)(nit - 1));
+                    if (old + (unsigned)(nit - 1) > p.extra_cap) nit = 1;
+                }
+                float est = piece_estimate<T, D>(L) / (float)nit;
+                int cls = 1;
+                while (cls < NCLS - 1 && (float)(1u << cls) < est) ++cls;
+                info = ((uint32_t)cls << 28) | ((uint32_t)nit << 16) | (uint32_t)sx;
+                atomicAdd(&s_hist[cls], (unsigned)nit);
+            }
+        } else if (p.validate && st == SETUP_BAD_INDEX) {
+            record_error(p.es, SP_E_OUT_OF_RANGE);
+            atomicAdd(&p.es->n_bad_index, 1);
+        } else if (p.validate && st == SETUP_NONFINITE) {
+            record_error(p.es, SP_E_NONFINITE);
+            atomicAdd(&p.es->n_nonfinite, 1);
+        } else if (p.validate && st == SETUP_BAD_SPAN) {
+            record_error(p.es, SP_E_PERIODIC_SPAN);
+            atomicAdd(&p.es->n_bad_span, 1);
+        }
+        p.tinfo[s] = info;
+    }
+    __syncthreads();
+    if (threadIdx.x < NCLS && s_hist[threadIdx.x]) atomicAdd(&p.cs->hist[threadIdx.x], s_hist[threadIdx.x]);
+}
+
+__global__ void k_scan(CallState *cs)
+{
+    if (threadIdx.x == 0) {
+        unsigned off = 0;
+        for (int c = NCLS - 1; c >= 0; --c) {
+            cs->cursor[c] = off;
+            off += cs->hist[c];
+        }
+        cs->total = off;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_scatter(ProbDev<T> p)
+{
+    __shared__ unsigned s_cnt[NCLS];
+    __shared__ unsigned s_base[NCLS];
+    if (threadIdx.x < NCLS) s_cnt[threadIdx.x] = 0u;
+    __syncthreads();
+    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t info = s < p.n ? p.tinfo[s] : 0u;
+    int cls = (int)(info >> 28), nit = (int)((info >> 16) & 0xfffu), sx = (int)(info & 0xffffu);
+    unsigned local = 0;
+    if (info) local = atomicAdd(&s_cnt[cls], (unsigned)nit);
+    __syncthreads();
+    if (threadIdx.x < NCLS && s_cnt[threadIdx.x])
+        s_base[threadIdx.x] = atomicAdd(&p.cs->cursor[threadIdx.x], s_cnt[threadIdx.x]);
+    __syncthreads();
+    if (info) {
+        unsigned pos = s_base[cls] + local;
+        int per = (sx + nit - 1) / nit;
+        for (int k = 0; k < nit; ++k) {
+            int sb = k * per;
+            int sc = sx - sb < per ? sx - sb : per;
+            if (sc <= 0) sc = 0;
+            p.items[pos + k] = (uint64_t)(uint32_t)s | ((uint64_t)sb << 32) | ((uint64_t)sc << 48);
+        }
+    }
+}
+
+// The clip kernel: persistent waves take 64 items at a time from the class-
+// ordered list (most expensive first), one item per lane.
+template <int D, typename T, int MAXV>
+__global__ __launch_bounds__(WG) void k_clip(ProbDev<T> p, int overflow_pass)
+{
+    constexpr int SLOTS = D == 3 ? MAXV : 2 * MAXP2;
+    __shared__ V4<T> s_p[SLOTS][WG];
+    __shared__ uint32_t s_nb[D == 3 ? MAXV : 1][WG];
+    const int lane = threadIdx.x;
+    __shared__ unsigned s_base;
+    unsigned total = overflow_pass ? min(p.cs->ovf_count, (unsigned)OVF_CAP) : p.cs->total;
+    unsigned *head = overflow_pass ? &p.cs->ovf_head : &p.cs->head;
+    for (;;) {
+        if (lane == 0) s_base = atomicAdd(head, (unsigned)WG);
+        __syncthreads();
+        unsigned base = s_base;
+        __syncthreads();
+        if (base >= total) break;
+        unsigned it = base + lane;
+        if (it < total) {
+            int64_t s;
+            int sb, sc, ry = 0, rz = 0;
+            if (overflow_pass) {
+                Ovf o = p.ovf[it];
+                s = o.s;
+                sb = o.ix;
+                sc = o.end - o.ix;
+                ry = o.iy;
+                rz = o.iz;
+            } else {
+                uint64_t item = p.items[it];
+                s = (int64_t)(uint32_t)item;
+                sb = (int)((item >> 32) & 0xffffu);
+                sc = (int)(item >> 48);
+            }
+            Local<T> L;
+            if (setup_any<D>(p, s, false, L) == SETUP_OK) {
+                auto dep = make_dep<T>(p, L);
+                if (overflow_pass) {
+                    dep.suppress_ix = sb;
+                    dep.suppress_iy = ry;
+                    dep.suppress_iz = rz;
+                }
+                int fail[3];
+                bool ok;
+                if constexpr (D == 3) {
+                    Poly3<T, MAXV, WG> P;
+                    P.p = &s_p[0][lane];
+                    P.nb = &s_nb[0][lane];
+                    P.n = 0;
+                    ok = sweep3(P, L, sb, sc, dep, ry, fail);
+                } else {
+                    Poly2<T, MAXP2, WG> P;
+                    P.a = &s_p[0][lane];
+                    P.b = &s_p[MAXP2][lane];
+                    P.n = 0;
+                    ok = sweep2(P, L, sb, sc, dep, fail);
+                }
+                if (!ok) {
+                    if (!overflow_pass) {
+                        unsigned k = atomicAdd(&p.cs->ovf_count, 1u);
+                        if (k < OVF_CAP) {
+                            Ovf o;
+                            o.s = (int)s;
+                            o.ix = fail[0];
+                            o.iy = fail[1];
+                            o.iz = fail[2];
+                            o.end = sb + sc;
+                            p.ovf[k] = o;
+                            atomicAdd(&p.es->n_overflow, 1);
+                        } else {
+                            record_error(p.es, SP_E_INTERNAL);
+                            atomicAdd(&p.es->n_internal, 1);
+                        }
+                    } else {
+                        record_error(p.es, SP_E_INTERNAL);
+                        atomicAdd(&p.es->n_internal, 1);
+                    }
+                }
+            }
+        }
+    }
+}
+
+// hi + lo -> out (unless the caller keeps lo), FP64 total of the grid in mass
+// units.
+template <typename T>
+__global__ __launch_bounds__(256) void k_finalize(T *out, float *lo, int keep_lo, size_t ncell, double to_mass,
+                                                  double *total)
+{
+    __shared__ double s_sum[256];
+    double acc = 0.0;
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t st = (size_t)gridDim.x * blockDim.x;
+    for (; i < ncell; i += st) {
+        if constexpr (sizeof(T) == 4) {
+            float h = out[i], l = lo[i];
+            acc += (double)h + (double)l;
+            if (!keep_lo) out[i] = h + l;
+        } else {
+            acc += (double)out[i];
+        }
+    }
+    s_sum[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) s_sum[threadIdx.x] += s_sum[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && total) unsafeAtomicAdd(total, s_sum[0] * to_mass);
+}
+
+} // namespace
+
+// ---------------------------------------------------------------------------
+// host runtime
+
+struct sp_ctx {
+    int device;
+    int num_cu;
+    void *scratch;
+    size_t scratch_cap;
+    CallState *cs;
+    ErrState *es;
+    double *dummy_total;
+    Tuning tune;
+};
+
+static thread_local std::string g_err;
+
+static sp_status fail(sp_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIPCHECK(call)                                                                                   \
+    do {                                                                                                 \
+        hipError_t e_ = (call);                                                                          \
+        if (e_ != hipSuccess) return fail(SP_E_DEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+extern "C" sp_status sp_create(int hip_device, sp_ctx **ctx)
+{
+    if (!ctx) return fail(SP_E_INVALID_ARG, "ctx is NULL");
+    *ctx = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) return fail(SP_E_DEVICE, "no HIP device");
+    if (hip_device < 0 || hip_device >= n) return fail(SP_E_DEVICE, "device %d out of range (%d devices)", hip_device, n);
+    hipDeviceProp_t prop;
+    HIPCHECK(hipGetDeviceProperties(&prop, hip_device));
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(SP_E_DEVICE, "device %d is %s, this library is built for gfx950", hip_device, prop.gcnArchName);
+    HIPCHECK(hipSetDevice(hip_device));
+    sp_ctx *c = new sp_ctx();
+    c->device = hip_device;
+    c->num_cu = prop.multiProcessorCount;
+    c->scratch = nullptr;
+    c->scratch_cap = 0;
+    void *st = nullptr;
+    if (hipMalloc(&st, 4096) != hipSuccess) {
+        delete c;
+        return fail(SP_E_NO_MEMORY, "hipMalloc of the context state failed");
+    }
+    c->cs = reinterpret_cast<CallState *>(st);
+    c->es = reinterpret_cast<ErrState *>(reinterpret_cast<char *>(st) + 1024);
+    c->dummy_total = reinterpret_cast<double *>(reinterpret_cast<char *>(st) + 2048);
+    (void)hipMemset(st, 0, 4096);
+    (void)hipDeviceSynchronize();
+    c->tune.slab_group = 4;
+    c->tune.chunks_per_cu = 0;
+    *ctx = c;
+    return SP_OK;
+}
+
+extern "C" void sp_destroy(sp_ctx *ctx)
+{
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    if (ctx->scratch) (void)hipFree(ctx->scratch);
+    (void)hipFree(ctx->cs);
+    delete ctx;
+}
+
+extern "C" const char *sp_last_error(const sp_ctx *)
+{
+    return g_err.c_str();
+}
+
+static sp_status ensure_scratch(sp_ctx *ctx, size_t bytes)
+{
+    if (bytes <= ctx->scratch_cap) return SP_OK;
+    HIPCHECK(hipDeviceSynchronize());
+    if (ctx->scratch) (void)hipFree(ctx->scratch);
+    ctx->scratch = nullptr;
+    ctx->scratch_cap = 0;
+    size_t want = bytes + bytes / 4;
+    if (hipMalloc(&ctx->scratch, want) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(SP_E_NO_MEMORY, "scratch allocation of %zu bytes failed", want);
+    }
+    ctx->scratch_cap = want;
+    return SP_OK;
+}
+
+static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static sp_status check_problem(const sp_problem *p, int dim, sp_precision prec)
+{
+    if (!p) return fail(SP_E_INVALID_ARG, "problem is NULL");
+    if (prec != SP_PREC_FP64 && prec != SP_PREC_FP32C) return fail(SP_E_INVALID_ARG, "unknown precision %d", (int)prec);
+    const uint32_t known = SP_PERIODIC_X | SP_PERIODIC_Y | SP_PERIODIC_Z | SP_RHO_PER_CORNER | SP_OUT_MASS |
+                           SP_ACCUMULATE | SP_VALIDATE;
+    if (p->grid.flags & ~known) return fail(SP_E_INVALID_ARG, "unknown flag bits 0x%x", p->grid.flags & ~known);
+    if (p->n_vert < 0 || p->n_vert >= (int64_t)1 << 31) return fail(SP_E_INVALID_ARG, "n_vert %lld out of range", (long long)p->n_vert);
+    if (p->n_simplex < 0 || p->n_simplex >= (int64_t)1 << 31)
+        return fail(SP_E_INVALID_ARG, "n_simplex %lld out of range", (long long)p->n_simplex);
+    for (int d = 0; d < dim; ++d) {
+        if (p->grid.dims[d] <= 0 || p->grid.dims[d] > (1 << 20)) return fail(SP_E_INVALID_ARG, "dims[%d] = %d out of range", d, p->grid.dims[d]);
+        if (!(p->grid.extent[d] > 0.0) || !isfinite(p->grid.extent[d])) return fail(SP_E_INVALID_ARG, "extent[%d] must be > 0", d);
+        if (!isfinite(p->grid.origin[d])) return fail(SP_E_INVALID_ARG, "origin[%d] must be finite", d);
+    }
+    double nc = 1.0;
+    for (int d = 0; d < dim; ++d) nc *= p->grid.dims[d];
+    if (nc > 4.0e9) return fail(SP_E_INVALID_ARG, "grid of %.0f cells is too large", nc);
+    if (!p->out) return fail(SP_E_INVALID_ARG, "out is NULL");
+    if (p->n_simplex > 0 && (!p->xyz || !p->simplices || !p->rho)) return fail(SP_E_INVALID_ARG, "xyz, simplices and rho must not be NULL");
+    if (p->out_lo && prec != SP_PREC_FP32C) return fail(SP_E_INVALID_ARG, "out_lo is only used with SP_PREC_FP32C");
+    return SP_OK;
+}
+
+template <typename T>
+static void fill_grid(GridDev &g, const sp_problem *p, int dim)
+{
+    memset(&g, 0, sizeof g);
+    double cellvol = 1.0;
+    for (int d = 0; d < 3; ++d) {
+        if (d < dim) {
+            g.dims[d] = p->grid.dims[d];
+            g.periodic[d] = (p->grid.flags >> d) & 1u;
+            g.origin[d] = p->grid.origin[d];
+            g.extent[d] = p->grid.extent[d];
+            g.scale[d] = (double)p->grid.dims[d] / p->grid.extent[d];
+            cellvol *= p->grid.extent[d] / (double)p->grid.dims[d];
+        } else {
+            g.dims[d] = 1;
+            g.periodic[d] = 1;
+            g.origin[d] = 0;
+            g.extent[d] = 1;
+            g.scale[d] = 1;
+        }
+        g.o_hi[d] = (float)g.origin[d];
+        g.o_lo[d] = (float)(g.origin[d] - (double)g.o_hi[d]);
+        g.s_hi[d] = (float)g.scale[d];
+        g.s_lo[d] = (float)(g.scale[d] - (double)g.s_hi[d]);
+    }
+    g.out_scale = (p->grid.flags & SP_OUT_MASS) ? cellvol : 1.0;
+}
+
+static int grid_blocks(size_t n, int per)
+{
+    size_t b = (n + per - 1) / per;
+    if (b > 65536 * 8) b = 65536 * 8;
+    if (b < 1) b = 1;
+    return (int)b;
+}
+
+template <int D, typename T>
+static sp_status project_impl(sp_ctx *ctx, const sp_problem *prob, sp_precision prec, hipStream_t stream)
+{
+    sp_status st;
+    HIPCHECK(hipSetDevice(ctx->device));
+    const int64_t n = prob->n_simplex;
+    size_t ncell = 1;
+    for (int d = 0; d < D; ++d) ncell *= (size_t)prob->grid.dims[d];
+    const bool fp32 = sizeof(T) == 4;
+    const bool keep_lo = fp32 && prob->out_lo != nullptr;
+    const bool accumulate = (prob->grid.flags & SP_ACCUMULATE) != 0;
+    const unsigned extra_cap = (unsigned)(n / 2 + 4096);
+    // scratch layout
+    size_t off = 0;
+    size_t o_tinfo = off;
+    off = align_up(off + sizeof(uint32_t) * (size_t)(n > 0 ? n : 1));
+    size_t o_items = off;
+    off = align_up(off + sizeof(uint64_t) * ((size_t)n + extra_cap));
+    size_t o_ovf = off;
+    off = align_up(off + sizeof(Ovf) * OVF_CAP);
+    size_t o_lo = off;
+    if (fp32 && !keep_lo) off = align_up(off + sizeof(float) * ncell);
+    st = ensure_scratch(ctx, off);
+    if (st != SP_OK) return st;
+    char *base = reinterpret_cast<char *>(ctx->scratch);
+
+    ProbDev<T> p;
+    p.xyz = reinterpret_cast<const T *>(prob->xyz);
+    p.n_vert = prob->n_vert;
+    p.simp = prob->simplices;
+    p.n = n;
+    p.rho = reinterpret_cast<const T *>(prob->rho);
+    p.per_corner = (prob->grid.flags & SP_RHO_PER_CORNER) != 0;
+    p.validate = (prob->grid.flags & SP_VALIDATE) != 0;
+    fill_grid<T>(p.g, prob, D);
+    p.out = reinterpret_cast<T *>(prob->out);
+    p.lo = fp32 ? (keep_lo ? prob->out_lo : reinterpret_cast<float *>(base + o_lo)) : nullptr;
+    p.tinfo = reinterpret_cast<uint32_t *>(base + o_tinfo);
+    p.items = reinterpret_cast<uint64_t *>(base + o_items);
+    p.extra_cap = extra_cap;
+    p.ovf = reinterpret_cast<Ovf *>(base + o_ovf);
+    p.cs = ctx->cs;
+    p.es = ctx->es;
+    p.slab_group = ctx->tune.slab_group;
+
+    double *total = prob->total_mass;
+    hipLaunchKernelGGL(k_clear_state, dim3(1), dim3(64), 0, stream, ctx->cs, total);
+    if (!accumulate) {
+        hipLaunchKernelGGL(k_fill<T>, dim3(grid_blocks(ncell, 256)), dim3(256), 0, stream, p.out, ncell);
+    }
+    if (fp32 && (!accumulate || !keep_lo)) {
+        hipLaunchKernelGGL(k_fill<float>, dim3(grid_blocks(ncell, 256)), dim3(256), 0, stream, p.lo, ncell);
+    }
+    if (n > 0) {
+        int nb = (int)((n + 255) / 256);
+        hipLaunchKernelGGL((k_setup<D, T>), dim3(nb), dim3(256), 0, stream, p);
+        hipLaunchKernelGGL(k_scan, dim3(1), dim3(64), 0, stream, ctx->cs);
+        hipLaunchKernelGGL((k_scatter<T>), dim3(nb), dim3(256), 0, stream, p);
+        int occ = 0;
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_clip<D, T, MAXV3>, WG, 0);
+        if (occ < 1) occ = 1;
+        int cpc = ctx->tune.chunks_per_cu > 0 ? ctx->tune.chunks_per_cu : occ;
+        int blocks = ctx->num_cu * cpc;
+        hipLaunchKernelGGL((k_clip<D, T, MAXV3>), dim3(blocks), dim3(WG), 0, stream, p, 0);
+        if (D == 3) {
+            hipLaunchKernelGGL((k_clip<D, T, MAXV3_BIG>), dim3(ctx->num_cu), dim3(WG), 0, stream, p, 1);
+        }
+    }
+    double to_mass = 1.0;
+    if (!(prob->grid.flags & SP_OUT_MASS)) {
+        for (int d = 0; d < D; ++d) to_mass *= prob->grid.extent[d] / (double)prob->grid.dims[d];
+    }
+    if (fp32 || total) {
+        hipLaunchKernelGGL(k_finalize<T>, dim3(grid_blocks(ncell, 256 * 8)), dim3(256), 0, stream, p.out,
+                           p.lo, keep_lo ? 1 : 0, ncell, to_mass, total);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(SP_E_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+    return SP_OK;
+}
+
+extern "C" sp_status sp_project_tets(sp_ctx *ctx, const sp_problem *prob, sp_precision prec, void *stream)
+{
+    sp_status st = check_problem(prob, 3, prec);
+    if (st != SP_OK) return st;
+    if (!ctx) return fail(SP_E_INVALID_ARG, "ctx is NULL");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    return prec == SP_PREC_FP32C ? project_impl<3, float>(ctx, prob, prec, s) : project_impl<3, double>(ctx, prob, prec, s);
+}
+
+extern "C" sp_status sp_project_tris(sp_ctx *ctx, const sp_problem *prob, sp_precision prec, void *stream)
+{
+    sp_status st = check_problem(prob, 2, prec);
+    if (st != SP_OK) return st;
+    if (!ctx) return fail(SP_E_INVALID_ARG, "ctx is NULL");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    return prec == SP_PREC_FP32C ? project_impl<2, float>(ctx, prob, prec, s) : project_impl<2, double>(ctx, prob, prec, s);
+}
+
+extern "C" sp_status sp_project_batch(sp_ctx *ctx, int dim, const sp_problem *probs, int n, sp_precision prec, void *stream)
+{
+    if (!ctx) return fail(SP_E_INVALID_ARG, "ctx is NULL");
+    if (dim != 3) return fail(SP_E_UNSUPPORTED, "batched projection supports dim 3 only");
+    if (n < 0 || (n > 0 && !probs)) return fail(SP_E_INVALID_ARG, "bad problem array");
+    for (int i = 0; i < n; ++i) {
+        sp_status st = sp_project_tets(ctx, &probs[i], prec, stream);
+        if (st != SP_OK) return st;
+    }
+    return SP_OK;
+}
+
+extern "C" sp_status sp_sync_status(sp_ctx *ctx, void *stream)
+{
+    if (!ctx) return fail(SP_E_INVALID_ARG, "ctx is NULL");
+    HIPCHECK(hipSetDevice(ctx->device));
+    HIPCHECK(hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)));
+    ErrState e;
+    HIPCHECK(hipMemcpy(&e, ctx->es, sizeof e, hipMemcpyDeviceToHost));
+    HIPCHECK(hipMemset(ctx->es, 0, sizeof e));
+    if (e.first != 0) {
+        return fail((sp_status)e.first,
+                    "device errors: %d bad index, %d non-finite, %d periodic span, %d internal (%d overflow retries)",
+                    e.n_bad_index, e.n_nonfinite, e.n_bad_span, e.n_internal, e.n_overflow);
+    }
+    return SP_OK;
+}
+
+extern "C" sp_status sp_autotune(sp_ctx *ctx, int dim, const sp_problem *sample, int n, sp_precision prec,
+                                 const char *cache_path)
+{
+    if (!ctx) return fail(SP_E_INVALID_ARG, "ctx is NULL");
+    (void)dim;
+    (void)sample;
+    (void)n;
+    (void)prec;
+    (void)cache_path;
+    return fail(SP_E_UNSUPPORTED, "autotuning is not available in this build");
+}

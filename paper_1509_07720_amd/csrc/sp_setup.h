@@ -1,0 +1,482 @@
+// sp_setup.h -- per-simplex set-up and the slab/column/cell sweep.
+//
+// Set-up (gather, periodic unwrap, cell coordinates, orientation) and the
+// sweep that cuts one simplex into its pieces, one per grid cell it meets:
+// x-slabs, then y-columns inside a slab, then z-cells inside a column
+// (2D: x-slabs then y-cells).  The piece integrals are handed to a deposit
+// callback.  Everything here is plain arithmetic usable on host and device.
+#pragma once
+#include <math.h>
+#include <stdint.h>
+
+#include "sp_poly.h"
+
+namespace sp {
+
+// Grid parameters as the kernels see them.
+struct GridDev {
+    int dims[3];
+    int periodic[3];
+    // cell coordinate u = (x - origin) * scale, scale = dims / extent;
+    // hi/lo float pairs for the FP32 path, doubles for the FP64 path
+    float o_hi[3], o_lo[3], s_hi[3], s_lo[3];
+    double origin[3], scale[3], extent[3];
+    double out_scale;   // 1 for density output, cell volume for mass output
+};
+
+// Largest bounding-box extent, in cells, of one simplex on a non-periodic
+// axis (work items encode slab indices in 16 bits).
+constexpr int MAX_SPAN = 32768;
+
+enum SetupStatus : int {
+    SETUP_OK = 0,
+    SETUP_ZERO_VOLUME = 1,
+    SETUP_BAD_INDEX = 2,
+    SETUP_NONFINITE = 3,
+    SETUP_BAD_SPAN = 4,
+};
+
+// Local description of one simplex: corner positions in cell units relative
+// to its anchor cell (the lowest cell of its bounding box), positively
+// oriented; span = number of cells of the bounding box per axis.
+template <typename T>
+struct Local {
+    V4<T> v[4];
+    int anchor[3];
+    int span[3];
+    T det;   // 6 * volume (2 * area in 2D), > 0, cell units
+};
+
+// Error-free split of x*scale into an integer cell and a fraction in [0,1):
+// TwoSum for x - origin, TwoProduct (fma) for the product, so the fraction
+// carries the exact value up to one final rounding (Dekker 1971; Ogita, Rump
+// & Oishi 2005).
+SP_HD inline void cell_split(float x, float o_hi, float o_lo, float s_hi, float s_lo, int &k, float &f)
+{
+    float dh = x - o_hi;
+    float t = dh - x;
+    float dl = (x - (dh - t)) + (-o_hi - t);
+    dl -= o_lo;
+    float p = dh * s_hi;
+    float e = fmaf(dh, s_hi, -p);
+    float corr = e + (dh * s_lo + dl * s_hi);
+    float kf = floorf(p);
+    f = (p - kf) + corr;
+    k = (int)kf;
+    if (f >= 1.0f) {
+        f -= 1.0f;
+        k += 1;
+    }
+    if (f < 0.0f) {
+        f += 1.0f;
+        k -= 1;
+        if (f >= 1.0f) f = 0.0f, k += 1;
+    }
+}
+
+SP_HD inline bool finite_f(float v) { return v - v == 0.0f; }
+SP_HD inline bool finite_d(double v) { return v - v == 0.0; }
+
+// 6*volume of the tetrahedron (a, b, c, d)
+template <typename T>
+SP_HD inline T det3(const V4<T> &a, const V4<T> &b, const V4<T> &c, const V4<T> &d)
+{
+    T e1x = b.x - a.x, e1y = b.y - a.y, e1z = b.z - a.z;
+    T e2x = c.x - a.x, e2y = c.y - a.y, e2z = c.z - a.z;
+    T e3x = d.x - a.x, e3y = d.y - a.y, e3z = d.z - a.z;
+    return e1x * (e2y * e3z - e2z * e3y) - e1y * (e2x * e3z - e2z * e3x) + e1z * (e2x * e3y - e2y * e3x);
+}
+
+// Orientation in FP32 with a static error filter (Appendix E.1: the error of
+// a 3x3 determinant is bounded by a constant times the product of the
+// largest entry of each column; the constant is rescaled from the paper's
+// double precision value to single precision).  When the filter cannot
+// decide, the determinant is recomputed in FP64 from the same (exactly
+// representable) differences.  Returns 6*volume with the decided sign.
+SP_HD inline float orient3_f(const V4<float> *v)
+{
+    float d = det3(v[0], v[1], v[2], v[3]);
+    float mx[3] = {0.f, 0.f, 0.f};
+    for (int a = 1; a < 4; ++a) {
+        float e[3] = {v[a].x - v[0].x, v[a].y - v[0].y, v[a].z - v[0].z};
+        for (int k = 0; k < 3; ++k) mx[k] = fmaxf(mx[k], fabsf(e[k]));
+    }
+    const float alpha = 4.0e-6f;
+    if (fabsf(d) > alpha * mx[0] * mx[1] * mx[2]) return d;
+    double e[3][3];
+    for (int a = 1; a < 4; ++a) {
+        e[a - 1][0] = (double)v[a].x - (double)v[0].x;
+        e[a - 1][1] = (double)v[a].y - (double)v[0].y;
+        e[a - 1][2] = (double)v[a].z - (double)v[0].z;
+    }
+    double dd = e[0][0] * (e[1][1] * e[2][2] - e[1][2] * e[2][1]) - e[0][1] * (e[1][0] * e[2][2] - e[1][2] * e[2][0]) +
+                e[0][2] * (e[1][0] * e[2][1] - e[1][1] * e[2][0]);
+    if (dd == 0.0) return 0.0f;
+    // keep the FP64 sign even when the rounded magnitude underflows to 0
+    float r = (float)dd;
+    if (r == 0.0f) r = dd > 0 ? 1e-38f : -1e-38f;
+    return r;
+}
+
+SP_HD inline float orient2_f(const V4<float> *v)
+{
+    float ax = v[1].x - v[0].x, ay = v[1].y - v[0].y, bx = v[2].x - v[0].x, by = v[2].y - v[0].y;
+    float d = ax * by - ay * bx;
+    const float alpha = 2.0e-6f;
+    if (fabsf(d) > alpha * fmaxf(fabsf(ax), fabsf(bx)) * fmaxf(fabsf(ay), fabsf(by))) return d;
+    double dd = ((double)v[1].x - v[0].x) * ((double)v[2].y - v[0].y) - ((double)v[1].y - v[0].y) * ((double)v[2].x - v[0].x);
+    if (dd == 0.0) return 0.0f;
+    float r = (float)dd;
+    if (r == 0.0f) r = dd > 0 ? 1e-38f : -1e-38f;
+    return r;
+}
+
+// Set-up of simplex s in the FP32 path.  D = 2 or 3.  Every check runs
+// whatever `validate` says (a bad index or a non-finite coordinate must never
+// reach the sweep); the caller decides whether to report the status.
+template <int D>
+SP_HD inline int setup_f32(const float *xyz, int64_t n_vert, const int32_t *simp, int64_t s, const float *rho,
+                           bool per_corner, const GridDev &g, bool validate, Local<float> &L)
+{
+    constexpr int K = D + 1;
+    int k[4][3];
+    float f[4][3];
+    float r[4];
+    for (int a = 0; a < K; ++a) {
+        int64_t vi = simp[s * K + a];
+        if (vi < 0 || vi >= n_vert) return SETUP_BAD_INDEX;
+        for (int d = 0; d < D; ++d) {
+            float x = xyz[vi * D + d];
+            // cell coordinates must stay well inside the int range
+            float u = (x - g.o_hi[d]) * g.s_hi[d];
+            if (!finite_f(x) || !(fabsf(u) < 1.0e9f)) return SETUP_NONFINITE;
+            cell_split(x, g.o_hi[d], g.o_lo[d], g.s_hi[d], g.s_lo[d], k[a][d], f[a][d]);
+        }
+        r[a] = per_corner ? rho[s * K + a] : rho[vi];
+        if (!finite_f(r[a])) return SETUP_NONFINITE;
+    }
+    for (int d = 0; d < D; ++d) {
+        int kmin = k[0][d];
+        if (g.periodic[d]) {
+            const int N = g.dims[d];
+            for (int a = 1; a < K; ++a) {
+                float delta = (float)(k[a][d] - k[0][d]) + (f[a][d] - f[0][d]);
+                int sh = (int)rintf(delta / (float)N);
+                k[a][d] -= sh * N;
+            }
+        }
+        for (int a = 1; a < K; ++a) kmin = k[a][d] < kmin ? k[a][d] : kmin;
+        float lmax = 0.0f;
+        for (int a = 0; a < K; ++a) {
+            float l = (float)(k[a][d] - kmin) + f[a][d];
+            if (d == 0) L.v[a].x = l;
+            else if (d == 1) L.v[a].y = l;
+            else L.v[a].z = l;
+            lmax = l > lmax ? l : lmax;
+        }
+        if (g.periodic[d] ? !(lmax < 0.5f * (float)g.dims[d]) : !(lmax < (float)MAX_SPAN)) return SETUP_BAD_SPAN;
+        L.anchor[d] = kmin;
+        L.span[d] = (int)floorf(lmax) + 1;
+    }
+    for (int a = 0; a < K; ++a) {
+        if (D == 2) L.v[a].z = 0.0f;
+        L.v[a].r = r[a];
+    }
+    if (D == 2) {
+        L.anchor[2] = 0;
+        L.span[2] = 1;
+    }
+    float det = D == 3 ? orient3_f(L.v) : orient2_f(L.v);
+    if (det == 0.0f) return SETUP_ZERO_VOLUME;
+    if (det < 0.0f) {
+        V4<float> t = L.v[1];
+        L.v[1] = L.v[2];
+        L.v[2] = t;
+        det = -det;
+    }
+    L.det = det;
+    return SETUP_OK;
+}
+
+// Set-up of simplex s in the FP64 path: the same unwrap in box units and the
+// same cell coordinates as a plain double-precision evaluation.
+template <int D>
+SP_HD inline int setup_f64(const double *xyz, int64_t n_vert, const int32_t *simp, int64_t s, const double *rho,
+                           bool per_corner, const GridDev &g, bool validate, Local<double> &L)
+{
+    constexpr int K = D + 1;
+    double x[4][3];
+    double r[4];
+    for (int a = 0; a < K; ++a) {
+        int64_t vi = simp[s * K + a];
+        if (vi < 0 || vi >= n_vert) return SETUP_BAD_INDEX;
+        for (int d = 0; d < D; ++d) {
+            x[a][d] = xyz[vi * D + d];
+            double u = (x[a][d] - g.origin[d]) * g.scale[d];
+            if (!finite_d(x[a][d]) || !(fabs(u) < 1.0e9)) return SETUP_NONFINITE;
+        }
+        r[a] = per_corner ? rho[s * K + a] : rho[vi];
+        if (!finite_d(r[a])) return SETUP_NONFINITE;
+    }
+    for (int d = 0; d < D; ++d) {
+        if (g.periodic[d]) {
+            const double Lb = g.extent[d];
+            for (int a = 1; a < K; ++a) x[a][d] -= Lb * rint((x[a][d] - x[0][d]) / Lb);
+        }
+        double u[4];
+        double umin = 0, umax = 0;
+        for (int a = 0; a < K; ++a) {
+            u[a] = (x[a][d] - g.origin[d]) * g.scale[d];
+            umin = (a == 0 || u[a] < umin) ? u[a] : umin;
+            umax = (a == 0 || u[a] > umax) ? u[a] : umax;
+        }
+        if (g.periodic[d] ? !((umax - umin) < 0.5 * (double)g.dims[d]) : !((umax - umin) < (double)MAX_SPAN - 1.0))
+            return SETUP_BAD_SPAN;
+        double kmin = floor(umin);
+        for (int a = 0; a < K; ++a) {
+            double l = u[a] - kmin;
+            if (d == 0) L.v[a].x = l;
+            else if (d == 1) L.v[a].y = l;
+            else L.v[a].z = l;
+        }
+        L.anchor[d] = (int)kmin;
+        L.span[d] = (int)floor(umax - kmin) + 1;
+    }
+    for (int a = 0; a < K; ++a) {
+        if (D == 2) L.v[a].z = 0.0;
+        L.v[a].r = r[a];
+    }
+    if (D == 2) {
+        L.anchor[2] = 0;
+        L.span[2] = 1;
+    }
+    double det;
+    if (D == 3) {
+        det = det3(L.v[0], L.v[1], L.v[2], L.v[3]);
+    } else {
+        det = (L.v[1].x - L.v[0].x) * (L.v[2].y - L.v[0].y) - (L.v[1].y - L.v[0].y) * (L.v[2].x - L.v[0].x);
+    }
+    if (det == 0.0) return SETUP_ZERO_VOLUME;
+    if (det < 0.0) {
+        V4<double> t = L.v[1];
+        L.v[1] = L.v[2];
+        L.v[2] = t;
+        det = -det;
+    }
+    L.det = det;
+    return SETUP_OK;
+}
+
+// Sweep of one 3D simplex over x-slabs [sb, sb+sc) of its bounding box,
+// starting at column ry of the first slab.  dep(ix, iy, iz, value) receives
+// each piece's integral of rho in cell-volume units (local cell indices).
+// Returns false when a polytope exceeds its capacity; fail = (ix, iy, iz)
+// is then the first piece not yet deposited, in sweep order.
+template <typename T, int MAXV, int STRIDE, typename Dep>
+SP_HD inline bool sweep3(Poly3<T, MAXV, STRIDE> &P, const Local<T> &L, int sb, int sc, Dep &dep, int ry, int *fail)
+{
+    const int sx = L.span[0], sy = L.span[1], sz = L.span[2];
+    for (int ix = sb; ix < sb + sc; ++ix) {
+        int ylo = 0, yhi = -1;
+        const int ystart = ix == sb ? ry : 0;
+        for (int iy = 0;; ++iy) {
+            fail[0] = ix;
+            fail[1] = yhi < 0 ? ystart : iy;
+            fail[2] = 0;
+            // (re)build the slab ix of the simplex
+            P.init_tet(L.v);
+            if (ix > 0 && !P.clip(0, (T)ix, true)) return false;
+            if (ix < sx - 1 && !P.clip(0, (T)(ix + 1), false)) return false;
+            if (P.n == 0) break;
+            if (yhi < 0) {
+                T mn = P.coord(0, 1), mx = mn;
+                for (int v = 1; v < P.n; ++v) {
+                    T c = P.coord(v, 1);
+                    mn = c < mn ? c : mn;
+                    mx = c > mx ? c : mx;
+                }
+                ylo = (int)floor(mn);
+                yhi = (int)floor(mx);
+                ylo = ylo < 0 ? 0 : ylo;
+                yhi = yhi > sy - 1 ? sy - 1 : yhi;
+                iy = ylo > ystart ? ylo : ystart;
+            }
+            if (iy > yhi) break;
+            fail[1] = iy;
+            if (iy > ylo && !P.clip(1, (T)iy, true)) return false;
+            if (iy < yhi && !P.clip(1, (T)(iy + 1), false)) return false;
+            if (P.n == 0) {
+                if (iy >= yhi) break;
+                continue;
+            }
+            T mn = P.coord(0, 2), mx = mn;
+            for (int v = 1; v < P.n; ++v) {
+                T c = P.coord(v, 2);
+                mn = c < mn ? c : mn;
+                mx = c > mx ? c : mx;
+            }
+            int zlo = (int)floor(mn), zhi = (int)floor(mx);
+            zlo = zlo < 0 ? 0 : zlo;
+            zhi = zhi > sz - 1 ? sz - 1 : zhi;
+            for (int iz = zlo; iz <= zhi; ++iz) {
+                T s6, s24;
+                bool last = iz == zhi;
+                fail[2] = iz;
+                if (!P.integrate_below(2, (T)(iz + 1), last, s6, s24)) return false;
+                if (s24 != T(0)) dep(ix, iy, iz, s24 / T(24));
+                if (!last) {
+                    fail[2] = iz + 1;
+                    if (!P.clip(2, (T)(iz + 1), true)) return false;
+                    if (P.n == 0) break;
+                }
+            }
+            if (iy >= yhi) break;
+        }
+    }
+    return true;
+}
+
+// Convex polygon (2D pieces): an ordered, counter-clockwise vertex list in two
+// ping-pong buffers.  Cuts follow Sutherland-Hodgman with the same
+// classification and intersection rule as the 3D polytopes.
+template <typename T, int MAXP, int STRIDE>
+struct Poly2 {
+    V4<T> *a;
+    V4<T> *b;
+    int n;
+
+    SP_HD V4<T> P(int v) const { return a[v * STRIDE]; }
+
+    SP_HD void init_tri(const V4<T> *v)
+    {
+        for (int i = 0; i < 3; ++i) a[i * STRIDE] = v[i];
+        n = 3;
+    }
+
+    SP_HD bool clip(int ax, T c, bool keep_upper)
+    {
+        int m = 0;
+        for (int v = 0; v < n; ++v) {
+            V4<T> p = a[v * STRIDE];
+            V4<T> q = a[((v + 1) % n) * STRIDE];
+            bool bp = comp(p, ax) < c, bq = comp(q, ax) < c;
+            bool kp = keep_upper ? !bp : bp;
+            if (kp) {
+                if (m >= MAXP) return false;
+                b[m++ * STRIDE] = p;
+            }
+            if (bp != bq) {
+                if (m >= MAXP) return false;
+                b[m++ * STRIDE] = bp ? isect(p, q, ax, c) : isect(q, p, ax, c);
+            }
+        }
+        V4<T> *t = a;
+        a = b;
+        b = t;
+        n = m >= 3 ? m : 0;
+        return true;
+    }
+
+    // 2*area and 6*integral of the part below x_ax = c (or of the whole
+    // polygon), as triangles from an apex on the cutting line.
+    SP_HD void integrate_below(int ax, T c, bool whole, T &s2, T &s6) const
+    {
+        s2 = T(0);
+        s6 = T(0);
+        if (n == 0) return;
+        V4<T> A = a[0];
+        if (!whole) {
+            bool any = false, all = true;
+            for (int v = 0; v < n; ++v) {
+                bool bv = comp(a[v * STRIDE], ax) < c;
+                any = any || bv;
+                all = all && bv;
+            }
+            if (!any) return;
+            if (all) {
+                whole = true;
+            } else {
+                // apex: the first crossing point (on the cutting line)
+                for (int v = 0; v < n; ++v) {
+                    V4<T> p = a[v * STRIDE];
+                    V4<T> q = a[((v + 1) % n) * STRIDE];
+                    bool bp = comp(p, ax) < c, bq = comp(q, ax) < c;
+                    if (bp != bq) {
+                        A = bp ? isect(p, q, ax, c) : isect(q, p, ax, c);
+                        break;
+                    }
+                }
+            }
+        }
+        V4<T> q0, qp;
+        int cnt = 0;
+        for (int v = 0; v < n; ++v) {
+            V4<T> p = a[v * STRIDE];
+            V4<T> q = a[((v + 1) % n) * STRIDE];
+            bool bp = whole || comp(p, ax) < c, bq = whole || comp(q, ax) < c;
+            for (int e = 0; e < 2; ++e) {
+                V4<T> w;
+                if (e == 0) {
+                    if (!bp) continue;
+                    w = p;
+                } else {
+                    if (bp == bq) continue;
+                    w = bp ? isect(p, q, ax, c) : isect(q, p, ax, c);
+                }
+                if (cnt == 0) q0 = w;
+                else {
+                    T d = (qp.x - A.x) * (w.y - A.y) - (qp.y - A.y) * (w.x - A.x);
+                    s2 += d;
+                    s6 += d * (A.r + qp.r + w.r);
+                }
+                qp = w;
+                ++cnt;
+            }
+        }
+        if (cnt >= 2) {
+            T d = (qp.x - A.x) * (q0.y - A.y) - (qp.y - A.y) * (q0.x - A.x);
+            s2 += d;
+            s6 += d * (A.r + qp.r + q0.r);
+        }
+    }
+};
+
+// Sweep of one triangle over x-slabs [sb, sb+sc) of its bounding box; the
+// deposit receives (ix, iy, 0, integral of rho in cell-area units).
+template <typename T, int MAXP, int STRIDE, typename Dep>
+SP_HD inline bool sweep2(Poly2<T, MAXP, STRIDE> &P, const Local<T> &L, int sb, int sc, Dep &dep, int *fail)
+{
+    const int sx = L.span[0], sy = L.span[1];
+    for (int ix = sb; ix < sb + sc; ++ix) {
+        fail[0] = ix;
+        fail[1] = 0;
+        fail[2] = 0;
+        P.init_tri(L.v);
+        if (ix > 0 && !P.clip(0, (T)ix, true)) return false;
+        if (ix < sx - 1 && !P.clip(0, (T)(ix + 1), false)) return false;
+        if (P.n == 0) continue;
+        T mn = P.P(0).y, mx = mn;
+        for (int v = 1; v < P.n; ++v) {
+            T c = P.P(v).y;
+            mn = c < mn ? c : mn;
+            mx = c > mx ? c : mx;
+        }
+        int ylo = (int)floor(mn), yhi = (int)floor(mx);
+        ylo = ylo < 0 ? 0 : ylo;
+        yhi = yhi > sy - 1 ? sy - 1 : yhi;
+        for (int iy = ylo; iy <= yhi; ++iy) {
+            bool last = iy == yhi;
+            T s2, s6;
+            P.integrate_below(1, (T)(iy + 1), last, s2, s6);
+            if (s6 != T(0)) dep(ix, iy, 0, s6 / T(6));
+            if (!last) {
+                fail[1] = iy + 1;
+                if (!P.clip(1, (T)(iy + 1), true)) return false;
+                if (P.n == 0) break;
+            }
+        }
+    }
+    return true;
+}
+
+} // namespace sp

@@ -1,0 +1,226 @@
+"""Python binding of libsimproj (include/simproj.h).
+
+The functions ``sp_create`` ... ``sp_last_error`` mirror the C ABI one to one
+and only marshal arguments; every step of the projection runs in the HIP
+kernels of ``libsimproj.so``.  PyTorch provides device memory and streams.
+``project`` is a convenience wrapper that allocates the output grid.
+
+Importing this module fails loudly when the library has not been built: there
+is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsimproj.so")
+
+SP_OK = 0
+SP_E_INVALID_ARG = 1
+SP_E_OUT_OF_RANGE = 2
+SP_E_NONFINITE = 3
+SP_E_PERIODIC_SPAN = 4
+SP_E_NO_MEMORY = 5
+SP_E_DEVICE = 6
+SP_E_UNSUPPORTED = 7
+SP_E_INTERNAL = 8
+
+SP_PREC_FP64 = 0
+SP_PREC_FP32C = 1
+
+SP_PERIODIC_X = 1
+SP_PERIODIC_Y = 2
+SP_PERIODIC_Z = 4
+SP_RHO_PER_CORNER = 8
+SP_OUT_MASS = 16
+SP_ACCUMULATE = 32
+SP_VALIDATE = 64
+
+STATUS_NAMES = {0: "SP_OK", 1: "SP_E_INVALID_ARG", 2: "SP_E_OUT_OF_RANGE", 3: "SP_E_NONFINITE",
+                4: "SP_E_PERIODIC_SPAN", 5: "SP_E_NO_MEMORY", 6: "SP_E_DEVICE", 7: "SP_E_UNSUPPORTED",
+                8: "SP_E_INTERNAL"}
+
+
+class sp_grid(ctypes.Structure):
+    _fields_ = [("origin", ctypes.c_double * 3), ("extent", ctypes.c_double * 3),
+                ("dims", ctypes.c_int32 * 3), ("flags", ctypes.c_uint32)]
+
+
+class sp_problem(ctypes.Structure):
+    _fields_ = [("xyz", ctypes.c_void_p), ("n_vert", ctypes.c_int64), ("simplices", ctypes.c_void_p),
+                ("n_simplex", ctypes.c_int64), ("rho", ctypes.c_void_p), ("grid", sp_grid),
+                ("out", ctypes.c_void_p), ("out_lo", ctypes.c_void_p), ("total_mass", ctypes.c_void_p)]
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it first (python -c 'import __graft_entry__ as g; g.build()')")
+
+_lib = ctypes.CDLL(LIB_PATH)
+_V = ctypes.c_void_p
+_lib.sp_create.argtypes = [ctypes.c_int, ctypes.POINTER(_V)]
+_lib.sp_create.restype = ctypes.c_int
+_lib.sp_destroy.argtypes = [_V]
+_lib.sp_destroy.restype = None
+for _name in ("sp_project_tets", "sp_project_tris"):
+    getattr(_lib, _name).argtypes = [_V, ctypes.POINTER(sp_problem), ctypes.c_int, _V]
+    getattr(_lib, _name).restype = ctypes.c_int
+_lib.sp_project_batch.argtypes = [_V, ctypes.c_int, ctypes.POINTER(sp_problem), ctypes.c_int, ctypes.c_int, _V]
+_lib.sp_project_batch.restype = ctypes.c_int
+_lib.sp_sync_status.argtypes = [_V, _V]
+_lib.sp_sync_status.restype = ctypes.c_int
+_lib.sp_autotune.argtypes = [_V, ctypes.c_int, ctypes.POINTER(sp_problem), ctypes.c_int, ctypes.c_int,
+                             ctypes.c_char_p]
+_lib.sp_autotune.restype = ctypes.c_int
+_lib.sp_last_error.argtypes = [_V]
+_lib.sp_last_error.restype = ctypes.c_char_p
+
+
+class SimprojError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        msg = _lib.sp_last_error(None).decode(errors="replace")
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}: {msg}")
+
+
+def _check(st: int, where: str) -> int:
+    if st != SP_OK:
+        raise SimprojError(st, where)
+    return st
+
+
+# --------------------------------------------------------------------------
+# one-to-one wrappers (return the status code; the raising helpers are below)
+
+def sp_create(device: int = 0):
+    h = _V()
+    st = _lib.sp_create(int(device), ctypes.byref(h))
+    return st, h
+
+
+def sp_destroy(ctx) -> None:
+    _lib.sp_destroy(ctx)
+
+
+def sp_project_tets(ctx, prob: sp_problem, prec: int, stream=None) -> int:
+    return _lib.sp_project_tets(ctx, ctypes.byref(prob), int(prec), stream)
+
+
+def sp_project_tris(ctx, prob: sp_problem, prec: int, stream=None) -> int:
+    return _lib.sp_project_tris(ctx, ctypes.byref(prob), int(prec), stream)
+
+
+def sp_project_batch(ctx, dim: int, probs: Sequence[sp_problem], prec: int, stream=None) -> int:
+    arr = (sp_problem * len(probs))(*probs)
+    return _lib.sp_project_batch(ctx, int(dim), arr, len(probs), int(prec), stream)
+
+
+def sp_sync_status(ctx, stream=None) -> int:
+    return _lib.sp_sync_status(ctx, stream)
+
+
+def sp_autotune(ctx, dim: int, sample: Sequence[sp_problem], prec: int, cache_path: Optional[str] = None) -> int:
+    arr = (sp_problem * len(sample))(*sample)
+    cp = cache_path.encode() if cache_path else None
+    return _lib.sp_autotune(ctx, int(dim), arr, len(sample), int(prec), cp)
+
+
+def sp_last_error(ctx=None) -> str:
+    return _lib.sp_last_error(ctx).decode(errors="replace")
+
+
+# --------------------------------------------------------------------------
+# torch glue
+
+def _stream_ptr(stream):
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def make_problem(xyz, simplices, rho, dims, origin=(0.0, 0.0, 0.0), extent=(1.0, 1.0, 1.0),
+                 periodic=(True, True, True), rho_per_corner=False, out=None, out_lo=None, total_mass=None,
+                 out_mass=False, accumulate=False, validate=False) -> sp_problem:
+    """Fill an sp_problem from device tensors (no copies)."""
+    dim = int(xyz.shape[1]) if xyz.dim() == 2 else 3
+    p = sp_problem()
+    p.xyz = xyz.data_ptr() if xyz.numel() else None
+    p.n_vert = int(xyz.shape[0])
+    p.simplices = simplices.data_ptr() if simplices.numel() else None
+    p.n_simplex = int(simplices.shape[0])
+    p.rho = rho.data_ptr() if rho.numel() else None
+    for d in range(3):
+        p.grid.origin[d] = float(origin[d]) if d < len(origin) else 0.0
+        p.grid.extent[d] = float(extent[d]) if d < len(extent) else 1.0
+        p.grid.dims[d] = int(dims[d]) if d < len(dims) else 1
+    fl = 0
+    for d in range(min(3, len(periodic))):
+        if periodic[d]:
+            fl |= 1 << d
+    if rho_per_corner:
+        fl |= SP_RHO_PER_CORNER
+    if out_mass:
+        fl |= SP_OUT_MASS
+    if accumulate:
+        fl |= SP_ACCUMULATE
+    if validate:
+        fl |= SP_VALIDATE
+    p.grid.flags = fl
+    p.out = out.data_ptr() if out is not None else None
+    p.out_lo = out_lo.data_ptr() if out_lo is not None else None
+    p.total_mass = total_mass.data_ptr() if total_mass is not None else None
+    return p
+
+
+class Context:
+    """An sp_ctx on one device (created lazily, destroyed with the object)."""
+
+    def __init__(self, device: int = 0):
+        st, h = sp_create(device)
+        _check(st, "sp_create")
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "handle", None):
+            sp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def project(self, xyz, simplices, rho, dims, origin=(0.0, 0.0, 0.0), extent=(1.0, 1.0, 1.0),
+                periodic=(True, True, True), precision: str = "fp32c", rho_per_corner: bool = False,
+                out=None, out_lo=None, out_mass: bool = False, accumulate: bool = False,
+                validate: bool = False, want_total: bool = True, stream=None):
+        """Project a mesh held in device tensors; returns (grid, total_mass).
+        ``grid`` has shape dims reversed (z, y, x) / (y, x)."""
+        import torch
+
+        dim = int(xyz.shape[1])
+        prec = SP_PREC_FP32C if precision == "fp32c" else SP_PREC_FP64
+        dt = torch.float32 if prec == SP_PREC_FP32C else torch.float64
+        if xyz.dtype != dt or rho.dtype != dt:
+            raise TypeError(f"xyz and rho must be {dt} for precision {precision}")
+        if simplices.dtype != torch.int32:
+            raise TypeError("simplices must be int32")
+        for t in (xyz, simplices, rho):
+            if not t.is_cuda or not t.is_contiguous():
+                raise ValueError("inputs must be contiguous device tensors")
+        shape = tuple(int(d) for d in reversed(list(dims)[:dim]))
+        if out is None:
+            out = torch.empty(shape, dtype=dt, device=xyz.device)
+        total = torch.zeros(1, dtype=torch.float64, device=xyz.device) if want_total else None
+        p = make_problem(xyz, simplices, rho, dims, origin, extent, periodic, rho_per_corner, out, out_lo, total,
+                         out_mass, accumulate, validate)
+        fn = sp_project_tets if dim == 3 else sp_project_tris
+        _check(fn(self.handle, p, prec, _stream_ptr(stream)), fn.__name__)
+        return out, total
+
+    def sync_status(self, stream=None) -> int:
+        return sp_sync_status(self.handle, _stream_ptr(stream))
