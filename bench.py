@@ -1,0 +1,197 @@
+#!/usr/bin/env python3
+"""Throughput of the exact simplex-to-grid projection on one MI355X.
+
+Workload: the 10M-tetrahedron soup onto a 256^3 periodic grid (volumes
+log-uniform over 1e-6..20 voxels, aspect ratios up to 50, float32 positions,
+per-corner densities), generated synthetically from a fixed seed.  One step
+is one complete sp_project_tets call: set-up and binning, single-cell
+deposits, clip-integrate-deposit of every other simplex, and the hi+lo merge
+with the FP64 total-mass reduction.  Inputs are resident in HBM before the
+timed region.  The same workload is also timed in FP64 mode.
+
+Prints one JSON line (see the "metric" field).  --gpus above 1 is refused:
+this build measures one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic work per deposited piece, FP32 operations: the cut that
+# separates the piece (about 6 new vertices x 10 flops: a division and four
+# fused multiply-adds for position and density), the classification of the
+# ~12 remaining vertices against the plane (12), and the integration of the
+# piece as a fan of ~12 tetrahedra (12 x 20 flops: a 3x3 determinant and the
+# density sum).  See the design notes for the derivation.
+FLOPS_PER_PIECE = 60 + 12 + 240
+PEAK_FP32_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def exact_total(prob) -> float:
+    from paper_1509_07720_amd import synth
+
+    tot = 0.0
+    S = prob["simplices"]
+    R = prob["rho"]
+    for s0 in range(0, S.shape[0], 1 << 21):
+        sub = S[s0:s0 + (1 << 21)]
+        P = synth.unwrapped_corners(prob["xyz"], sub, prob["extent"], prob["periodic"])
+        r = R[s0:s0 + (1 << 21)] if prob["rho_per_corner"] else R[sub]
+        tot += float(np.sum(np.abs(synth.signed_volumes(P)) * r.mean(axis=1)))
+    return tot
+
+
+def time_steps(ctx, args_dev, steps, warmup, prec):
+    import torch
+
+    xyz, simp, rho, out, total, kw = args_dev
+    for _ in range(warmup):
+        ctx.project(xyz, simp, rho, kw["dims"], precision=prec, rho_per_corner=True, out=out, out_mass=True)
+    torch.cuda.synchronize()
+    ctx.profile(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.project(xyz, simp, rho, kw["dims"], precision=prec, rho_per_corner=True, out=out, out_mass=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = ctx.profile_read()
+    ctx.profile(0)
+    return (t1 - t0) / steps, prof
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n-tets", type=int, default=10_000_000)
+    ap.add_argument("--grid", type=int, default=256)
+    ap.add_argument("--cpu-sample", type=int, default=200_000, help="tets projected by the CPU oracle baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (--gpus must be 1)", file=sys.stderr)
+        return 2
+
+    import torch
+
+    from paper_1509_07720_amd import simproj, synth
+
+    t = time.time()
+    prob = synth.tet_soup(n_tets=args.n_tets, grid=args.grid, seed=3)
+    log(f"generated {args.n_tets} tets in {time.time() - t:.1f}s")
+    dev = torch.device("cuda:0")
+    n = args.n_tets
+    dims = [args.grid] * 3
+    xyz32 = torch.from_numpy(np.ascontiguousarray(prob["xyz"], dtype=np.float32)).to(dev)
+    simp = torch.from_numpy(np.ascontiguousarray(prob["simplices"], dtype=np.int32)).to(dev)
+    rho32 = torch.from_numpy(np.ascontiguousarray(prob["rho"], dtype=np.float32)).to(dev)
+    out32 = torch.empty(tuple(dims), dtype=torch.float32, device=dev)
+    ctx = simproj.Context(0)
+    exact = exact_total(synth.as_float32(prob))
+    log("inputs resident; timing FP32C")
+
+    # piece count: one extra call with counting on, outside the timed region
+    ctx.profile(2)
+    ctx.project(xyz32, simp, rho32, dims, precision="fp32c", rho_per_corner=True, out=out32, out_mass=True)
+    pieces = ctx.profile_read()["pieces"]
+    ctx.profile(0)
+
+    sec, prof = time_steps(ctx, (xyz32, simp, rho32, out32, None, dict(dims=dims)), args.steps, args.warmup, "fp32c")
+    g, total = ctx.project(xyz32, simp, rho32, dims, precision="fp32c", rho_per_corner=True, out=out32,
+                           out_mass=True)
+    assert ctx.sync_status() == simproj.SP_OK, simproj.sp_last_error()
+    mass_err = abs(float(total.cpu()[0]) - exact) / exact
+    value = n / sec
+    clip_ms = prof["ms_clip"] / max(prof["calls"], 1)
+    achieved = pieces * FLOPS_PER_PIECE / (clip_ms * 1e-3) / 1e12
+    in_bytes = xyz32.numel() * 4 + simp.numel() * 4 + rho32.numel() * 4
+    grid_bytes = 2 * out32.numel() * 4  # hi and lo grids
+    hbm_gbs = (in_bytes + grid_bytes) / sec / 1e9
+    log(f"fp32c: {sec * 1e3:.3f} ms/step, {value:.3e} tets/s, clip {clip_ms:.3f} ms, pieces {pieces}, "
+        f"mass err {mass_err:.2e}")
+    stages = {k: round(v / max(prof["calls"], 1), 4) for k, v in prof.items() if k.startswith("ms_")}
+
+    fp64 = None
+    if not args.no_fp64:
+        xyz64 = xyz32.double()
+        rho64 = rho32.double()
+        out64 = torch.empty(tuple(dims), dtype=torch.float64, device=dev)
+        sec64, prof64 = time_steps(ctx, (xyz64, simp, rho64, out64, None, dict(dims=dims)), args.steps,
+                                   args.warmup, "fp64")
+        _, total64 = ctx.project(xyz64, simp, rho64, dims, precision="fp64", rho_per_corner=True, out=out64,
+                                 out_mass=True)
+        assert ctx.sync_status() == simproj.SP_OK, simproj.sp_last_error()
+        err64 = abs(float(total64.cpu()[0]) - exact) / exact
+        fp64 = {"value": n / sec64, "ms_per_step": sec64 * 1e3, "mass_rel_err": err64,
+                "clip_ms": prof64["ms_clip"] / max(prof64["calls"], 1),
+                "hbm_gbs": (xyz64.numel() * 8 + simp.numel() * 4 + rho64.numel() * 8 + out64.numel() * 8) / sec64 / 1e9}
+        log(f"fp64: {sec64 * 1e3:.3f} ms/step, {n / sec64:.3e} tets/s, mass err {err64:.2e}")
+        del xyz64, rho64, out64
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+
+        k = min(args.cpu_sample, n)
+        sub = dict(synth.as_float32(prob), simplices=np.ascontiguousarray(prob["simplices"][:k]),
+                   rho=np.ascontiguousarray(np.asarray(prob["rho"], dtype=np.float32)[:k].astype(np.float64)))
+        threads = len(os.sched_getaffinity(0))
+        if os.environ.get("OMP_NUM_THREADS"):
+            threads = min(threads, int(os.environ["OMP_NUM_THREADS"]))
+        t = time.perf_counter()
+        oracle.project(sub, nthreads=threads, coverage=False)
+        dt = time.perf_counter() - t
+        cpu = {"value": k / dt, "unit": "simplices/s", "cores": threads, "kind": "oracle",
+               "sample": f"first {k} tets of the workload, FP64 brute-force clip of every candidate cell, "
+                         f"{dt:.1f} s wall on {threads} threads"}
+        log(f"cpu oracle: {k / dt:.3e} tets/s on {threads} threads ({dt:.1f}s)")
+
+    line = {
+        "metric": "simplices projected/sec + HBM GB/s at 10M tets->256^3, FP32 vs FP64 at stated error",
+        "value": value,
+        "unit": "simplices/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"tet-soup-{n}-to-{args.grid}^3", "n_simplex": n, "grid": dims,
+                   "precision": "fp32c", "rho": "per-corner", "seed": 3},
+        "hbm_gbs": hbm_gbs,
+        "mass_rel_err": mass_err,
+        "pieces": pieces,
+        "stages_ms": stages,
+        "fp64": fp64,
+        "roofline": {"bound": "alu", "kernel": "k_clip", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "flops_per_piece": FLOPS_PER_PIECE, "clip_ms": clip_ms},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+    ctx.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -140,6 +140,33 @@ sp_status sp_sync_status(sp_ctx *ctx, void *stream);
 sp_status sp_autotune(sp_ctx *ctx, int dim, const sp_problem *sample, int n, sp_precision prec,
                       const char *cache_path);
 
+/* Per-stage device times of the projection calls made while profiling is
+ * on, from HIP events recorded on each call's own stream around its kernels
+ * (the tracing hook of this library; it adds no synchronisation to the
+ * calls themselves). */
+typedef struct {
+    int calls;               /* projection calls recorded                          */
+    double ms_call;          /* first kernel start to last kernel end, summed       */
+    double ms_fill;          /* zeroing of the output and state                     */
+    double ms_setup;         /* set-up, single-cell deposits, class histogram       */
+    double ms_bin;           /* class offsets and scatter of the work items         */
+    double ms_clip;          /* clip-integrate-deposit over all work items          */
+    double ms_clip_retry;    /* items resumed with larger polytopes                 */
+    double ms_finalize;      /* hi+lo merge and total-mass reduction                */
+    long long pieces;        /* pieces deposited by the last call (mode 2 only)     */
+    long long items;         /* work items of the last call                         */
+} sp_profile;
+
+/* on = 0: off; 1: record stage times; 2: also count the pieces deposited
+ * (one extra atomic per work item, so keep it out of timed runs).  Turning
+ * recording on clears what was recorded before.  Applies to the calls that
+ * follow. */
+sp_status sp_profile_enable(sp_ctx *ctx, int on);
+
+/* Wait for the device, then return the times accumulated since profiling
+ * was enabled and clear them. */
+sp_status sp_profile_read(sp_ctx *ctx, sp_profile *out);
+
 /* Message describing the last error returned on this thread. */
 const char *sp_last_error(const sp_ctx *ctx);
 

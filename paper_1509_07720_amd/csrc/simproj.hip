@@ -50,6 +50,8 @@ struct CallState {
     unsigned extra;
     unsigned ovf_count;
     unsigned ovf_head;
+    unsigned pad;
+    unsigned long long pieces;
 };
 
 // Error state, kept until sp_sync_status reads and clears it.
@@ -91,10 +93,12 @@ struct DepF32 {
     int periodic[3];
     float scale;
     int suppress_iy, suppress_iz, suppress_ix;  // resume: skip pieces before this one
+    int count;
 
     __device__ void operator()(int ix, int iy, int iz, float v)
     {
         if (ix == suppress_ix && (iy < suppress_iy || (iy == suppress_iy && iz < suppress_iz))) return;
+        ++count;
         int c[3] = {anchor[0] + ix, anchor[1] + iy, anchor[2] + iz};
         for (int d = 0; d < 3; ++d) {
             if (periodic[d]) {
@@ -121,10 +125,12 @@ struct DepF64 {
     int periodic[3];
     double scale;
     int suppress_iy, suppress_iz, suppress_ix;
+    int count;
 
     __device__ void operator()(int ix, int iy, int iz, double v)
     {
         if (ix == suppress_ix && (iy < suppress_iy || (iy == suppress_iy && iz < suppress_iz))) return;
+        ++count;
         int c[3] = {anchor[0] + ix, anchor[1] + iy, anchor[2] + iz};
         for (int d = 0; d < 3; ++d) {
             if (periodic[d]) {
@@ -172,6 +178,7 @@ struct ProbDev {
     CallState *cs;
     ErrState *es;
     int slab_group;
+    int count_pieces;
 };
 
 template <int D>
@@ -202,6 +209,7 @@ __device__ inline DepF32 make_dep<float>(const ProbDev<float> &p, const Local<fl
     d.suppress_ix = -1;
     d.suppress_iy = 0;
     d.suppress_iz = 0;
+    d.count = 0;
     return d;
 }
 template <>
@@ -218,6 +226,7 @@ __device__ inline DepF64 make_dep<double>(const ProbDev<double> &p, const Local<
     d.suppress_ix = -1;
     d.suppress_iy = 0;
     d.suppress_iz = 0;
+    d.count = 0;
     return d;
 }
 
@@ -286,6 +295,7 @@ __global__ __launch_bounds__(256) void k_setup(ProbDev<T> p)
                 T val = D == 3 ? L.det * rs / T(24) : L.det * rs / T(6);
                 auto dep = make_dep<T>(p, L);
                 dep(0, 0, 0, val);
+                if (p.count_pieces) atomicAdd(&p.cs->pieces, 1ull);
             } else {
                 int sx = L.span[0];
                 int G = p.slab_group;
@@ -414,6 +424,7 @@ __global__ __launch_bounds__(WG) void k_clip(ProbDev<T> p, int overflow_pass)
                     P.n = 0;
                     ok = sweep2(P, L, sb, sc, dep, fail);
                 }
+                if (p.count_pieces && dep.count) atomicAdd(&p.cs->pieces, (unsigned long long)dep.count);  // counting runs only
                 if (!ok) {
                     if (!overflow_pass) {
                         unsigned k = atomicAdd(&p.cs->ovf_count, 1u);
@@ -473,6 +484,8 @@ __global__ __launch_bounds__(256) void k_finalize(T *out, float *lo, int keep_lo
 // ---------------------------------------------------------------------------
 // host runtime
 
+enum Stage { ST_FILL, ST_SETUP, ST_BIN, ST_CLIP, ST_RETRY, ST_FINAL, ST_N };
+
 struct sp_ctx {
     int device;
     int num_cu;
@@ -482,9 +495,35 @@ struct sp_ctx {
     ErrState *es;
     double *dummy_total;
     Tuning tune;
+    int profiling;
+    int prof_calls;
+    // (start, end) events per recorded stage and per whole call
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[ST_N];
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_call;
+};
+
+// Event pair around one stage of a call (no-op unless profiling).
+struct StageTimer {
+    sp_ctx *ctx;
+    hipStream_t s;
+    hipEvent_t a = nullptr, b = nullptr;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> *dst;
+    StageTimer(sp_ctx *c, hipStream_t st, std::vector<std::pair<hipEvent_t, hipEvent_t>> *d) : ctx(c), s(st), dst(d)
+    {
+        if (ctx->profiling && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess)
+            (void)hipEventRecord(a, s);
+    }
+    ~StageTimer()
+    {
+        if (a && b) {
+            (void)hipEventRecord(b, s);
+            dst->push_back({a, b});
+        }
+    }
 };
 
 static thread_local std::string g_err;
+static void drop_events(sp_ctx *ctx);
 
 static sp_status fail(sp_status st, const char *fmt, ...)
 {
@@ -532,6 +571,8 @@ extern "C" sp_status sp_create(int hip_device, sp_ctx **ctx)
     (void)hipDeviceSynchronize();
     c->tune.slab_group = 4;
     c->tune.chunks_per_cu = 0;
+    c->profiling = 0;
+    c->prof_calls = 0;
     *ctx = c;
     return SP_OK;
 }
@@ -541,6 +582,7 @@ extern "C" void sp_destroy(sp_ctx *ctx)
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
+    drop_events(ctx);
     if (ctx->scratch) (void)hipFree(ctx->scratch);
     (void)hipFree(ctx->cs);
     delete ctx;
@@ -673,28 +715,48 @@ static sp_status project_impl(sp_ctx *ctx, const sp_problem *prob, sp_precision 
     p.cs = ctx->cs;
     p.es = ctx->es;
     p.slab_group = ctx->tune.slab_group;
+    p.count_pieces = ctx->profiling >= 2;
 
     double *total = prob->total_mass;
-    hipLaunchKernelGGL(k_clear_state, dim3(1), dim3(64), 0, stream, ctx->cs, total);
-    if (!accumulate) {
-        hipLaunchKernelGGL(k_fill<T>, dim3(grid_blocks(ncell, 256)), dim3(256), 0, stream, p.out, ncell);
-    }
-    if (fp32 && (!accumulate || !keep_lo)) {
-        hipLaunchKernelGGL(k_fill<float>, dim3(grid_blocks(ncell, 256)), dim3(256), 0, stream, p.lo, ncell);
+    if (ctx->profiling) ctx->prof_calls++;
+    StageTimer whole(ctx, stream, &ctx->ev_call);
+    {
+        StageTimer t(ctx, stream, &ctx->ev[ST_FILL]);
+        hipLaunchKernelGGL(k_clear_state, dim3(1), dim3(64), 0, stream, ctx->cs, total);
+        if (!accumulate) {
+            hipLaunchKernelGGL(k_fill<T>, dim3(grid_blocks(ncell, 256)), dim3(256), 0, stream, p.out, ncell);
+        }
+        if (fp32 && (!accumulate || !keep_lo)) {
+            hipLaunchKernelGGL(k_fill<float>, dim3(grid_blocks(ncell, 256)), dim3(256), 0, stream, p.lo, ncell);
+        }
     }
     if (n > 0) {
         int nb = (int)((n + 255) / 256);
-        hipLaunchKernelGGL((k_setup<D, T>), dim3(nb), dim3(256), 0, stream, p);
-        hipLaunchKernelGGL(k_scan, dim3(1), dim3(64), 0, stream, ctx->cs);
-        hipLaunchKernelGGL((k_scatter<T>), dim3(nb), dim3(256), 0, stream, p);
+        {
+            StageTimer t(ctx, stream, &ctx->ev[ST_SETUP]);
+            hipLaunchKernelGGL((k_setup<D, T>), dim3(nb), dim3(256), 0, stream, p);
+        }
+        {
+            StageTimer t(ctx, stream, &ctx->ev[ST_BIN]);
+            hipLaunchKernelGGL(k_scan, dim3(1), dim3(64), 0, stream, ctx->cs);
+            hipLaunchKernelGGL((k_scatter<T>), dim3(nb), dim3(256), 0, stream, p);
+        }
         int occ = 0;
         (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_clip<D, T, MAXV3>, WG, 0);
         if (occ < 1) occ = 1;
         int cpc = ctx->tune.chunks_per_cu > 0 ? ctx->tune.chunks_per_cu : occ;
         int blocks = ctx->num_cu * cpc;
-        hipLaunchKernelGGL((k_clip<D, T, MAXV3>), dim3(blocks), dim3(WG), 0, stream, p, 0);
-        if (D == 3) {
-            hipLaunchKernelGGL((k_clip<D, T, MAXV3_BIG>), dim3(ctx->num_cu), dim3(WG), 0, stream, p, 1);
+        {
+            StageTimer t(ctx, stream, &ctx->ev[ST_CLIP]);
+            hipLaunchKernelGGL((k_clip<D, T, MAXV3>), dim3(blocks), dim3(WG), 0, stream, p, 0);
+        }
+        {
+            StageTimer t(ctx, stream, &ctx->ev[ST_RETRY]);
+            if (D == 3) {
+                hipLaunchKernelGGL((k_clip<D, T, MAXV3_BIG>), dim3(ctx->num_cu), dim3(WG), 0, stream, p, 1);
+            } else {
+                hipLaunchKernelGGL((k_clip<D, T, MAXV3>), dim3(ctx->num_cu), dim3(WG), 0, stream, p, 1);
+            }
         }
     }
     double to_mass = 1.0;
@@ -702,6 +764,7 @@ static sp_status project_impl(sp_ctx *ctx, const sp_problem *prob, sp_precision 
         for (int d = 0; d < D; ++d) to_mass *= prob->grid.extent[d] / (double)prob->grid.dims[d];
     }
     if (fp32 || total) {
+        StageTimer t(ctx, stream, &ctx->ev[ST_FINAL]);
         hipLaunchKernelGGL(k_finalize<T>, dim3(grid_blocks(ncell, 256 * 8)), dim3(256), 0, stream, p.out,
                            p.lo, keep_lo ? 1 : 0, ncell, to_mass, total);
     }
@@ -753,6 +816,58 @@ extern "C" sp_status sp_sync_status(sp_ctx *ctx, void *stream)
                     "device errors: %d bad index, %d non-finite, %d periodic span, %d internal (%d overflow retries)",
                     e.n_bad_index, e.n_nonfinite, e.n_bad_span, e.n_internal, e.n_overflow);
     }
+    return SP_OK;
+}
+
+static void drop_events(sp_ctx *ctx)
+{
+    for (int k = 0; k <= ST_N; ++k) {
+        auto &v = k < ST_N ? ctx->ev[k] : ctx->ev_call;
+        for (auto &e : v) {
+            (void)hipEventDestroy(e.first);
+            (void)hipEventDestroy(e.second);
+        }
+        v.clear();
+    }
+    ctx->prof_calls = 0;
+}
+
+extern "C" sp_status sp_profile_enable(sp_ctx *ctx, int on)
+{
+    if (!ctx) return fail(SP_E_INVALID_ARG, "ctx is NULL");
+    HIPCHECK(hipSetDevice(ctx->device));
+    if (on) {
+        HIPCHECK(hipDeviceSynchronize());
+        drop_events(ctx);
+    }
+    ctx->profiling = on < 0 ? 0 : (on > 2 ? 2 : on);
+    return SP_OK;
+}
+
+extern "C" sp_status sp_profile_read(sp_ctx *ctx, sp_profile *out)
+{
+    if (!ctx || !out) return fail(SP_E_INVALID_ARG, "ctx or out is NULL");
+    HIPCHECK(hipSetDevice(ctx->device));
+    HIPCHECK(hipDeviceSynchronize());
+    memset(out, 0, sizeof *out);
+    double *dst[ST_N] = {&out->ms_fill, &out->ms_setup, &out->ms_bin, &out->ms_clip, &out->ms_clip_retry,
+                         &out->ms_finalize};
+    for (int k = 0; k <= ST_N; ++k) {
+        auto &v = k < ST_N ? ctx->ev[k] : ctx->ev_call;
+        double acc = 0.0;
+        for (auto &e : v) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, e.first, e.second) == hipSuccess) acc += ms;
+        }
+        if (k < ST_N) *dst[k] = acc;
+        else out->ms_call = acc;
+    }
+    out->calls = ctx->prof_calls;
+    CallState cs;
+    HIPCHECK(hipMemcpy(&cs, ctx->cs, sizeof cs, hipMemcpyDeviceToHost));
+    out->pieces = (long long)cs.pieces;
+    out->items = (long long)cs.total;
+    drop_events(ctx);
     return SP_OK;
 }
 

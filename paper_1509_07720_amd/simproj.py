@@ -54,6 +54,13 @@ class sp_problem(ctypes.Structure):
                 ("out", ctypes.c_void_p), ("out_lo", ctypes.c_void_p), ("total_mass", ctypes.c_void_p)]
 
 
+class sp_profile(ctypes.Structure):
+    _fields_ = [("calls", ctypes.c_int), ("ms_call", ctypes.c_double), ("ms_fill", ctypes.c_double),
+                ("ms_setup", ctypes.c_double), ("ms_bin", ctypes.c_double), ("ms_clip", ctypes.c_double),
+                ("ms_clip_retry", ctypes.c_double), ("ms_finalize", ctypes.c_double),
+                ("pieces", ctypes.c_longlong), ("items", ctypes.c_longlong)]
+
+
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it first (python -c 'import __graft_entry__ as g; g.build()')")
 
@@ -73,6 +80,10 @@ _lib.sp_sync_status.restype = ctypes.c_int
 _lib.sp_autotune.argtypes = [_V, ctypes.c_int, ctypes.POINTER(sp_problem), ctypes.c_int, ctypes.c_int,
                              ctypes.c_char_p]
 _lib.sp_autotune.restype = ctypes.c_int
+_lib.sp_profile_enable.argtypes = [_V, ctypes.c_int]
+_lib.sp_profile_enable.restype = ctypes.c_int
+_lib.sp_profile_read.argtypes = [_V, ctypes.POINTER(sp_profile)]
+_lib.sp_profile_read.restype = ctypes.c_int
 _lib.sp_last_error.argtypes = [_V]
 _lib.sp_last_error.restype = ctypes.c_char_p
 
@@ -124,6 +135,16 @@ def sp_autotune(ctx, dim: int, sample: Sequence[sp_problem], prec: int, cache_pa
     arr = (sp_problem * len(sample))(*sample)
     cp = cache_path.encode() if cache_path else None
     return _lib.sp_autotune(ctx, int(dim), arr, len(sample), int(prec), cp)
+
+
+def sp_profile_enable(ctx, on: int) -> int:
+    return _lib.sp_profile_enable(ctx, int(on))
+
+
+def sp_profile_read(ctx):
+    prof = sp_profile()
+    st = _lib.sp_profile_read(ctx, ctypes.byref(prof))
+    return st, prof
 
 
 def sp_last_error(ctx=None) -> str:
@@ -224,3 +245,11 @@ class Context:
 
     def sync_status(self, stream=None) -> int:
         return sp_sync_status(self.handle, _stream_ptr(stream))
+
+    def profile(self, on: int) -> None:
+        _check(sp_profile_enable(self.handle, on), "sp_profile_enable")
+
+    def profile_read(self) -> dict:
+        st, prof = sp_profile_read(self.handle)
+        _check(st, "sp_profile_read")
+        return {k: getattr(prof, k) for k, _ in sp_profile._fields_}
