@@ -155,6 +155,7 @@ typedef struct {
     double ms_finalize;      /* hi+lo merge and total-mass reduction                */
     long long pieces;        /* pieces deposited by the last call (mode 2 only)     */
     long long items;         /* work items of the last call                         */
+    int clip_blocks;         /* persistent blocks of the last call's clip launch    */
 } sp_profile;
 
 /* on = 0: off; 1: record stage times; 2: also count the pieces deposited

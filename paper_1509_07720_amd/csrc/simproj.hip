@@ -88,9 +88,10 @@ __device__ inline void record_error(ErrState *e, int code)
 struct DepF32 {
     float *hi;
     float *lo;
-    int anchor[3];
+    int anchor[3];   // along the sweep axes
     int dims[3];
     int periodic[3];
+    size_t stride[3];
     float scale;
     int suppress_iy, suppress_iz, suppress_ix;  // resume: skip pieces before this one
     int count;
@@ -108,7 +109,7 @@ struct DepF32 {
                 return;
             }
         }
-        size_t idx = (size_t)c[0] + (size_t)dims[0] * ((size_t)c[1] + (size_t)dims[1] * (size_t)c[2]);
+        size_t idx = (size_t)c[0] * stride[0] + (size_t)c[1] * stride[1] + (size_t)c[2] * stride[2];
         float x = v * scale;
         float old = unsafeAtomicAdd(hi + idx, x);
         float s = old + x;
@@ -120,9 +121,10 @@ struct DepF32 {
 
 struct DepF64 {
     double *out;
-    int anchor[3];
+    int anchor[3];   // along the sweep axes
     int dims[3];
     int periodic[3];
+    size_t stride[3];
     double scale;
     int suppress_iy, suppress_iz, suppress_ix;
     int count;
@@ -140,7 +142,7 @@ struct DepF64 {
                 return;
             }
         }
-        size_t idx = (size_t)c[0] + (size_t)dims[0] * ((size_t)c[1] + (size_t)dims[1] * (size_t)c[2]);
+        size_t idx = (size_t)c[0] * stride[0] + (size_t)c[1] * stride[1] + (size_t)c[2] * stride[2];
         unsafeAtomicAdd(out + idx, v * scale);
     }
 };
@@ -192,18 +194,23 @@ __device__ inline int setup_any(const ProbDev<double> &p, int64_t s, bool valida
     return setup_f64<D>(p.xyz, p.n_vert, p.simp, s, p.rho, p.per_corner != 0, p.g, validate, L);
 }
 
+constexpr SweepOrder kIdentity = {{0, 1, 2}};
+
+// Deposit for a simplex swept in order o (L already relabelled by o).
 template <typename T>
-__device__ inline typename DepFor<T>::type make_dep(const ProbDev<T> &p, const Local<T> &L);
+__device__ inline typename DepFor<T>::type make_dep(const ProbDev<T> &p, const Local<T> &L, const SweepOrder &o);
 template <>
-__device__ inline DepF32 make_dep<float>(const ProbDev<float> &p, const Local<float> &L)
+__device__ inline DepF32 make_dep<float>(const ProbDev<float> &p, const Local<float> &L, const SweepOrder &o)
 {
     DepF32 d;
     d.hi = p.out;
     d.lo = p.lo;
+    const size_t st[3] = {1, (size_t)p.g.dims[0], (size_t)p.g.dims[0] * (size_t)p.g.dims[1]};
     for (int k = 0; k < 3; ++k) {
         d.anchor[k] = L.anchor[k];
-        d.dims[k] = p.g.dims[k];
-        d.periodic[k] = p.g.periodic[k];
+        d.dims[k] = p.g.dims[o.ax[k]];
+        d.periodic[k] = p.g.periodic[o.ax[k]];
+        d.stride[k] = st[o.ax[k]];
     }
     d.scale = (float)p.g.out_scale;
     d.suppress_ix = -1;
@@ -213,14 +220,16 @@ __device__ inline DepF32 make_dep<float>(const ProbDev<float> &p, const Local<fl
     return d;
 }
 template <>
-__device__ inline DepF64 make_dep<double>(const ProbDev<double> &p, const Local<double> &L)
+__device__ inline DepF64 make_dep<double>(const ProbDev<double> &p, const Local<double> &L, const SweepOrder &o)
 {
     DepF64 d;
     d.out = p.out;
+    const size_t st[3] = {1, (size_t)p.g.dims[0], (size_t)p.g.dims[0] * (size_t)p.g.dims[1]};
     for (int k = 0; k < 3; ++k) {
         d.anchor[k] = L.anchor[k];
-        d.dims[k] = p.g.dims[k];
-        d.periodic[k] = p.g.periodic[k];
+        d.dims[k] = p.g.dims[o.ax[k]];
+        d.periodic[k] = p.g.periodic[o.ax[k]];
+        d.stride[k] = st[o.ax[k]];
     }
     d.scale = p.g.out_scale;
     d.suppress_ix = -1;
@@ -293,11 +302,11 @@ __global__ __launch_bounds__(256) void k_setup(ProbDev<T> p)
                 // the whole simplex lies in one cell: deposit its mass
                 T rs = L.v[0].r + L.v[1].r + L.v[2].r + (D == 3 ? L.v[3].r : T(0));
                 T val = D == 3 ? L.det * rs / T(24) : L.det * rs / T(6);
-                auto dep = make_dep<T>(p, L);
+                auto dep = make_dep<T>(p, L, kIdentity);
                 dep(0, 0, 0, val);
                 if (p.count_pieces) atomicAdd(&p.cs->pieces, 1ull);
             } else {
-                int sx = L.span[0];
+                int sx = D == 3 ? L.span[sweep_order(L).ax[0]] : L.span[0];
                 int G = p.slab_group;
                 int nit = (sx + G - 1) / G;
                 if (nit > 1) {
@@ -401,9 +410,11 @@ __global__ __launch_bounds__(WG) void k_clip(ProbDev<T> p, int overflow_pass)
                 sb = (int)((item >> 32) & 0xffffu);
                 sc = (int)(item >> 48);
             }
-            Local<T> L;
-            if (setup_any<D>(p, s, false, L) == SETUP_OK) {
-                auto dep = make_dep<T>(p, L);
+            Local<T> L0;
+            if (setup_any<D>(p, s, false, L0) == SETUP_OK) {
+                const SweepOrder ord = D == 3 ? sweep_order(L0) : kIdentity;
+                const Local<T> L = D == 3 ? permuted(L0, ord) : L0;
+                auto dep = make_dep<T>(p, L, ord);
                 if (overflow_pass) {
                     dep.suppress_ix = sb;
                     dep.suppress_iy = ry;
@@ -415,7 +426,7 @@ __global__ __launch_bounds__(WG) void k_clip(ProbDev<T> p, int overflow_pass)
                     Poly3<T, MAXV, WG> P;
                     P.p = &s_p[0][lane];
                     P.nb = &s_nb[0][lane];
-                    P.n = 0;
+                    P.live = 0u;
                     ok = sweep3(P, L, sb, sc, dep, ry, fail);
                 } else {
                     Poly2<T, MAXP2, WG> P;
@@ -497,6 +508,7 @@ struct sp_ctx {
     Tuning tune;
     int profiling;
     int prof_calls;
+    int last_clip_blocks;
     // (start, end) events per recorded stage and per whole call
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[ST_N];
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_call;
@@ -571,8 +583,12 @@ extern "C" sp_status sp_create(int hip_device, sp_ctx **ctx)
     (void)hipDeviceSynchronize();
     c->tune.slab_group = 4;
     c->tune.chunks_per_cu = 0;
+    // launch-shape overrides for tuning experiments
+    if (const char *e = getenv("SIMPROJ_SLAB_GROUP")) c->tune.slab_group = atoi(e) > 0 ? atoi(e) : 4;
+    if (const char *e = getenv("SIMPROJ_CLIP_BLOCKS_PER_CU")) c->tune.chunks_per_cu = atoi(e) > 0 ? atoi(e) : 0;
     c->profiling = 0;
     c->prof_calls = 0;
+    c->last_clip_blocks = 0;
     *ctx = c;
     return SP_OK;
 }
@@ -746,6 +762,7 @@ static sp_status project_impl(sp_ctx *ctx, const sp_problem *prob, sp_precision 
         if (occ < 1) occ = 1;
         int cpc = ctx->tune.chunks_per_cu > 0 ? ctx->tune.chunks_per_cu : occ;
         int blocks = ctx->num_cu * cpc;
+        ctx->last_clip_blocks = blocks;
         {
             StageTimer t(ctx, stream, &ctx->ev[ST_CLIP]);
             hipLaunchKernelGGL((k_clip<D, T, MAXV3>), dim3(blocks), dim3(WG), 0, stream, p, 0);
@@ -867,6 +884,7 @@ extern "C" sp_status sp_profile_read(sp_ctx *ctx, sp_profile *out)
     HIPCHECK(hipMemcpy(&cs, ctx->cs, sizeof cs, hipMemcpyDeviceToHost));
     out->pieces = (long long)cs.pieces;
     out->items = (long long)cs.total;
+    out->clip_blocks = ctx->last_clip_blocks;
     drop_events(ctx);
     return SP_OK;
 }

@@ -54,6 +54,19 @@ SP_HD inline void set_comp(V4<T> &p, int ax, T v)
     else p.z = v;
 }
 
+// Reciprocal used by the cut: the hardware reciprocal in FP32 (about one
+// ulp; both sides of a cut call the same function with the same operands,
+// so the shared points stay bit-identical), an exact division in FP64.
+SP_HD inline float sp_rcp(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_rcpf(x);
+#else
+    return 1.0f / x;
+#endif
+}
+SP_HD inline double sp_rcp(double x) { return 1.0 / x; }
+
 // Point where segment (a, b) meets the plane x_ax = c, for a strictly below
 // and b at or above the plane.  The interpolation starts from the nearer end
 // (halving the rounding of the long-edge case); the coordinate along ax is
@@ -63,21 +76,17 @@ template <typename T>
 SP_HD inline V4<T> isect(const V4<T> &a, const V4<T> &b, int ax, T c)
 {
     T ca = comp(a, ax), cb = comp(b, ax);
-    T den = cb - ca;
-    T ta = (c - ca) / den;
+    T rd = sp_rcp(cb - ca);
+    T ta = (c - ca) * rd;
+    bool from_a = ta <= T(0.5);
+    const V4<T> &s = from_a ? a : b;
+    const V4<T> &e = from_a ? b : a;
+    T t = from_a ? ta : (cb - c) * rd;
     V4<T> q;
-    if (ta <= T(0.5)) {
-        q.x = a.x + ta * (b.x - a.x);
-        q.y = a.y + ta * (b.y - a.y);
-        q.z = a.z + ta * (b.z - a.z);
-        q.r = a.r + ta * (b.r - a.r);
-    } else {
-        T tb = (cb - c) / den;
-        q.x = b.x + tb * (a.x - b.x);
-        q.y = b.y + tb * (a.y - b.y);
-        q.z = b.z + tb * (a.z - b.z);
-        q.r = b.r + tb * (a.r - b.r);
-    }
+    q.x = s.x + t * (e.x - s.x);
+    q.y = s.y + t * (e.y - s.y);
+    q.z = s.z + t * (e.z - s.z);
+    q.r = s.r + t * (e.r - s.r);
     set_comp(q, ax, c);
     return q;
 }
@@ -92,16 +101,21 @@ SP_HD inline int slot_of(uint32_t nb, int v)
     return nbr(nb, 0) == v ? 0 : (nbr(nb, 1) == v ? 1 : 2);
 }
 SP_HD inline uint32_t pack3(int a, int b, int c) { return (uint32_t)a | ((uint32_t)b << 8) | ((uint32_t)c << 16); }
+SP_HD inline int lowbit(uint32_t m) { return __builtin_ctz(m); }
 
 // Vertex storage with a stride: on the GPU each lane's polytope is spread
 // over LDS with stride = lanes per block, so that lanes touching the same
-// slot hit consecutive words.
+// slot hit consecutive words.  Slots in use are marked in `live`; a cut
+// writes its new vertices into slots that were free before it and frees the
+// removed ones, so vertices never move and neighbour indices never need
+// renumbering.
 template <typename T, int MAXV, int STRIDE>
 struct Poly3 {
     static_assert(MAXV <= 32, "vertex masks are 32-bit");
+    static constexpr uint32_t SLOTS = MAXV == 32 ? 0xffffffffu : ((1u << MAXV) - 1u);
     V4<T> *p;
     uint32_t *nb;
-    int n;
+    uint32_t live;
 
     SP_HD V4<T> P(int v) const { return p[v * STRIDE]; }
     SP_HD void setP(int v, const V4<T> &q) { p[v * STRIDE] = q; }
@@ -112,6 +126,7 @@ struct Poly3 {
         const T *q = reinterpret_cast<const T *>(&p[v * STRIDE]);
         return q[ax];
     }
+    SP_HD bool empty() const { return live == 0u; }
 
     // A positively oriented tetrahedron (det(v1-v0, v2-v0, v3-v0) > 0).
     SP_HD void init_tet(const V4<T> *v)
@@ -121,14 +136,28 @@ struct Poly3 {
         setN(1, pack3(2, 3, 0));
         setN(2, pack3(0, 3, 1));
         setN(3, pack3(1, 2, 0));
-        n = 4;
+        live = 0xfu;
     }
 
     SP_HD uint32_t below_mask(int ax, T c) const
     {
         uint32_t m = 0;
-        for (int v = 0; v < n; ++v) m |= (uint32_t)(coord(v, ax) < c) << v;
+        for (uint32_t w = live; w; w &= w - 1u) {
+            int v = lowbit(w);
+            m |= (uint32_t)(coord(v, ax) < c) << v;
+        }
         return m;
+    }
+
+    SP_HD void range(int ax, T &mn, T &mx) const
+    {
+        int v0 = lowbit(live);
+        mn = mx = coord(v0, ax);
+        for (uint32_t w = live & (live - 1u); w; w &= w - 1u) {
+            T c = coord(lowbit(w), ax);
+            mn = c < mn ? c : mn;
+            mx = c > mx ? c : mx;
+        }
     }
 
     // Keep the part with x_ax >= c (keep_upper) or x_ax < c.  Returns false
@@ -136,156 +165,155 @@ struct Poly3 {
     // polytope graph (the polytope is then left unusable).
     SP_HD bool clip(int ax, T c, bool keep_upper)
     {
-        const uint32_t full = n >= 32 ? 0xffffffffu : ((1u << n) - 1u);
         uint32_t below = below_mask(ax, c);
-        uint32_t keep = keep_upper ? (~below & full) : below;
-        if (keep == full) return true;
-        if (keep == 0) {
-            n = 0;
+        uint32_t keep = keep_upper ? (live & ~below) : below;
+        if (keep == live) return true;
+        if (keep == 0u) {
+            live = 0u;
             return true;
         }
-        const int n0 = n;
-        int m = n0;
-        for (int v = 0; v < n0; ++v) {
-            if (!((keep >> v) & 1u)) continue;
+        uint32_t freem = ~live & SLOTS;
+        uint32_t fresh = 0u;
+        for (uint32_t w = keep; w; w &= w - 1u) {
+            const int v = lowbit(w);
             uint32_t nbv = N(v);
-            bool changed = false;
+            const uint32_t nb0 = nbv;
+            const V4<T> pv = P(v);
             for (int i = 0; i < 3; ++i) {
-                int w = nbr(nbv, i);
-                if ((keep >> w) & 1u) continue;
-                if (m >= MAXV) return false;
-                V4<T> pv = P(v), pw = P(w);
-                V4<T> q = keep_upper ? isect(pw, pv, ax, c) : isect(pv, pw, ax, c);
-                setP(m, q);
-                setN(m, pack3(v, v, v));
-                nbv = set_nbr(nbv, i, m);
-                changed = true;
-                ++m;
+                int x = nbr(nb0, i);
+                if ((keep >> x) & 1u) continue;
+                if (freem == 0u) return false;
+                const int u = lowbit(freem);
+                freem &= freem - 1u;
+                fresh |= 1u << u;
+                const V4<T> px = P(x);
+                setP(u, keep_upper ? isect(px, pv, ax, c) : isect(pv, px, ax, c));
+                setN(u, pack3(v, v, v));
+                nbv = set_nbr(nbv, i, u);
             }
-            if (changed) setN(v, nbv);
+            if (nbv != nb0) setN(v, nbv);
         }
-        // link the new vertices around the cap: walk each one's facet through
-        // kept vertices until the next new vertex
-        for (int u = n0; u < m; ++u) {
-            int prev = u, cur = nbr(N(u), 0);
-            int guard = 0;
-            for (;;) {
-                uint32_t nbc = N(cur);
-                int j = slot_of(nbc, prev);
-                int nxt = nbr(nbc, (j + 1) % 3);
-                prev = cur;
-                cur = nxt;
-                if (cur >= n0) break;
-                if (++guard > 2 * MAXV) return false;
+        // link the new vertices around the cap: from each one, walk its
+        // facet through kept vertices to the next new vertex.  One flat loop
+        // over all walk steps keeps the lanes of a wave in step.
+        uint32_t todo = fresh;
+        int u = lowbit(todo);
+        int prev = u, cur = nbr(N(u), 0);
+        int guard = 0;
+        while (todo) {
+            uint32_t nbc = N(cur);
+            int j = slot_of(nbc, prev);
+            int nxt = nbr(nbc, (j + 1) % 3);
+            prev = cur;
+            cur = nxt;
+            if ((fresh >> cur) & 1u) {
+                setN(u, set_nbr(N(u), 2, cur));
+                setN(cur, set_nbr(N(cur), 1, u));
+                todo &= todo - 1u;
+                if (todo) {
+                    u = lowbit(todo);
+                    prev = u;
+                    cur = nbr(N(u), 0);
+                }
             }
-            setN(u, set_nbr(N(u), 2, cur));
-            setN(cur, set_nbr(N(cur), 1, u));
+            if (++guard > 4 * MAXV * MAXV) return false;
         }
-        // compact: survivors are the kept old vertices then the new ones
-        const int nk = __builtin_popcount(keep);
-        int dst = 0;
-        for (int v = 0; v < m; ++v) {
-            if (v < n0 && !((keep >> v) & 1u)) continue;
-            uint32_t nbv = N(v);
-            uint32_t out = 0;
-            for (int i = 0; i < 3; ++i) {
-                int w = nbr(nbv, i);
-                int wn = w < n0 ? __builtin_popcount(keep & ((1u << w) - 1u)) : nk + (w - n0);
-                out |= (uint32_t)wn << (8 * i);
-            }
-            if (dst != v) setP(dst, P(v));
-            setN(dst, out);
-            ++dst;
-        }
-        n = dst;
+        live = keep | fresh;
         return true;
     }
 
     // Integral of the carried density over the part below x_ax = c (or over
     // the whole polytope when whole is true).  Returns 6*volume in s6 and
-    // 24*integral in s24 (both in the polytope's coordinate units; their sign
-    // is the orientation convention, positive for this vertex ordering).
+    // 24*integral in s24 (positive for this vertex ordering).  Every directed
+    // edge is visited exactly once: a facet is walked from its first
+    // unvisited directed edge until it closes; its part below the plane is
+    // emitted in order (Sutherland-Hodgman) and fanned from its first emitted
+    // point, each fan triangle closing a tetrahedron with the apex A, a point
+    // of the cap (so the cap facet itself adds nothing).
     SP_HD bool integrate_below(int ax, T c, bool whole, T &s6, T &s24) const
     {
         s6 = T(0);
         s24 = T(0);
-        if (n == 0) return true;
-        const uint32_t full = n >= 32 ? 0xffffffffu : ((1u << n) - 1u);
-        uint32_t below = whole ? full : below_mask(ax, c);
-        if (below == 0) return true;
-        if (below == full) whole = true;
-        V4<T> A;
-        if (whole) {
-            A = P(0);
-        } else {
-            // apex: a point of the cap (any crossing edge)
+        if (live == 0u) return true;
+        uint32_t below = whole ? live : below_mask(ax, c);
+        if (below == 0u) return true;
+        if (below == live) whole = true;
+        V4<T> A = P(lowbit(live));
+        if (!whole) {
             bool found = false;
-            for (int v = 0; v < n && !found; ++v) {
-                if (!((below >> v) & 1u)) continue;
-                uint32_t nbv = N(v);
+            for (uint32_t w = below; w && !found; w &= w - 1u) {
+                const int v = lowbit(w);
+                const uint32_t nbv = N(v);
                 for (int i = 0; i < 3; ++i) {
-                    int w = nbr(nbv, i);
-                    if (!((below >> w) & 1u)) {
-                        A = isect(P(v), P(w), ax, c);
+                    const int x = nbr(nbv, i);
+                    if (!((below >> x) & 1u)) {
+                        A = isect(P(v), P(x), ax, c);
                         found = true;
                         break;
                     }
                 }
             }
         }
-        uint32_t mk[3] = {0u, 0u, 0u};
-        for (int vs = 0; vs < n; ++vs) {
-            for (int ps = 0; ps < 3; ++ps) {
-                if ((mk[ps] >> vs) & 1u) continue;
-                int vcur = vs, pc = ps;
-                V4<T> q0, qp;
-                int cnt = 0;
-                V4<T> a = P(vcur);
-                bool ba = (below >> vcur) & 1u;
-                int guard = 0;
-                for (;;) {
-                    mk[pc] |= 1u << vcur;
-                    uint32_t nbc = N(vcur);
-                    int vnext = nbr(nbc, pc);
-                    V4<T> b = P(vnext);
-                    bool bb = (below >> vnext) & 1u;
-                    // emitted points of this edge: a (if below), then the
-                    // crossing point (if the edge crosses)
-                    for (int e = 0; e < 2; ++e) {
-                        V4<T> q;
-                        if (e == 0) {
-                            if (!ba) continue;
-                            q = a;
-                        } else {
-                            if (ba == bb) continue;
-                            q = ba ? isect(a, b, ax, c) : isect(b, a, ax, c);
-                        }
-                        if (cnt == 0) {
-                            q0 = q;
-                        } else if (cnt >= 2) {
-                            // tet (A, q0, q, qp)
-                            T e1x = q0.x - A.x, e1y = q0.y - A.y, e1z = q0.z - A.z;
-                            T e2x = q.x - A.x, e2y = q.y - A.y, e2z = q.z - A.z;
-                            T e3x = qp.x - A.x, e3y = qp.y - A.y, e3z = qp.z - A.z;
-                            T d = e1x * (e2y * e3z - e2z * e3y) - e1y * (e2x * e3z - e2z * e3x) +
-                                  e1z * (e2x * e3y - e2y * e3x);
-                            s6 += d;
-                            s24 += d * (A.r + q0.r + q.r + qp.r);
-                        }
-                        qp = q;
-                        ++cnt;
-                    }
-                    if (vnext == vs) break;
-                    int np = slot_of(N(vnext), vcur);
-                    pc = (np + 1) % 3;
-                    vcur = vnext;
-                    a = b;
-                    ba = bb;
-                    if (++guard > 2 * MAXV) return false;
-                }
+        uint32_t un0 = live, un1 = live, un2 = live;
+        int vs = 0, vcur = 0, pc = 0, cnt = 0;
+        bool open = false, ba = false;
+        V4<T> a;
+        T e0x = 0, e0y = 0, e0z = 0, r0 = 0, epx = 0, epy = 0, epz = 0, rp = 0;
+        auto acc = [&](const V4<T> &q) {
+            const T ex = q.x - A.x, ey = q.y - A.y, ez = q.z - A.z;
+            if (cnt == 0) {
+                e0x = ex;
+                e0y = ey;
+                e0z = ez;
+                r0 = q.r;
+            } else if (cnt >= 2) {
+                const T cx = ey * epz - ez * epy;
+                const T cy = ez * epx - ex * epz;
+                const T cz = ex * epy - ey * epx;
+                const T d = e0x * cx + e0y * cy + e0z * cz;
+                s6 += d;
+                s24 += d * (A.r + r0 + q.r + rp);
+            }
+            epx = ex;
+            epy = ey;
+            epz = ez;
+            rp = q.r;
+            ++cnt;
+        };
+        const int steps = 3 * __builtin_popcount(live);
+        for (int it = 0; it < steps; ++it) {
+            if (!open) {
+                const uint32_t any = un0 | un1 | un2;
+                if (any == 0u) return false;
+                const int v = lowbit(any);
+                pc = ((un0 >> v) & 1u) ? 0 : (((un1 >> v) & 1u) ? 1 : 2);
+                vs = v;
+                vcur = v;
+                cnt = 0;
+                open = true;
+                a = P(vcur);
+                ba = (below >> vcur) & 1u;
+            }
+            const uint32_t bit = 1u << vcur;
+            un0 &= pc == 0 ? ~bit : ~0u;
+            un1 &= pc == 1 ? ~bit : ~0u;
+            un2 &= pc == 2 ? ~bit : ~0u;
+            const int vnext = nbr(N(vcur), pc);
+            const V4<T> b = P(vnext);
+            const bool bb = (below >> vnext) & 1u;
+            if (ba) acc(a);
+            if (ba != bb) acc(ba ? isect(a, b, ax, c) : isect(b, a, ax, c));
+            if (vnext == vs) {
+                open = false;
+            } else {
+                const int np = slot_of(N(vnext), vcur);
+                pc = (np + 1) % 3;
+                vcur = vnext;
+                a = b;
+                ba = bb;
             }
         }
-        return true;
+        return !open;
     }
 };
 

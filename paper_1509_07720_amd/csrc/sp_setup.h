@@ -267,70 +267,142 @@ SP_HD inline int setup_f64(const double *xyz, int64_t n_vert, const int32_t *sim
     return SETUP_OK;
 }
 
-// Sweep of one 3D simplex over x-slabs [sb, sb+sc) of its bounding box,
-// starting at column ry of the first slab.  dep(ix, iy, iz, value) receives
-// each piece's integral of rho in cell-volume units (local cell indices).
-// Returns false when a polytope exceeds its capacity; fail = (ix, iy, iz)
-// is then the first piece not yet deposited, in sweep order.
+// Order in which a simplex is swept: outermost axis first, innermost last.
+// The innermost axis is the one of largest extent, which makes the columns
+// (and so the polytope rebuilds) fewest.
+struct SweepOrder {
+    int ax[3];
+};
+
+template <typename T>
+SP_HD inline SweepOrder sweep_order(const Local<T> &L)
+{
+    SweepOrder o;
+    int a = 0, b = 1, c = 2;
+    // sort axes by span, ascending; ties keep x, y, z order
+    if (L.span[b] < L.span[a]) { int t = a; a = b; b = t; }
+    if (L.span[c] < L.span[b]) { int t = b; b = c; c = t; }
+    if (L.span[b] < L.span[a]) { int t = a; a = b; b = t; }
+    o.ax[0] = a;
+    o.ax[1] = b;
+    o.ax[2] = c;
+    return o;
+}
+
+// The simplex with its axes relabelled so that sweep axis k becomes local
+// axis k (orientation restored by a vertex swap when the relabelling is odd).
+template <typename T>
+SP_HD inline Local<T> permuted(const Local<T> &L, const SweepOrder &o)
+{
+    Local<T> M = L;
+    for (int k = 0; k < 4; ++k) {
+        const T c[3] = {L.v[k].x, L.v[k].y, L.v[k].z};
+        M.v[k].x = c[o.ax[0]];
+        M.v[k].y = c[o.ax[1]];
+        M.v[k].z = c[o.ax[2]];
+    }
+    for (int d = 0; d < 3; ++d) {
+        M.span[d] = L.span[o.ax[d]];
+        M.anchor[d] = L.anchor[o.ax[d]];
+    }
+    // a transposition of two axes flips the orientation; the three cyclic
+    // orders keep it
+    const bool odd = !((o.ax[0] == 0 && o.ax[1] == 1) || (o.ax[0] == 1 && o.ax[1] == 2) || (o.ax[0] == 2 && o.ax[1] == 0));
+    if (odd) {
+        V4<T> t = M.v[1];
+        M.v[1] = M.v[2];
+        M.v[2] = t;
+    }
+    return M;
+}
+
+// Sweep of one 3D simplex over the slabs [sb, sb+sc) of its outermost axis,
+// starting at column ry of the first slab.  dep(i0, i1, i2, value) receives
+// each piece's integral of rho in cell-volume units (local cell indices
+// along the sweep axes).
+//
+// The sweep is one flat loop whose every step first builds the next column
+// polytope if the previous one is finished (the simplex cut by the planes of
+// slab i0 and column i1) and then cuts off and integrates one piece, so that
+// the lanes of a wave advance together whatever their slab, column and cell
+// counts.  Returns false when a polytope exceeds its capacity; fail =
+// (i0, i1, i2) is then the first piece not yet deposited, in sweep order.
 template <typename T, int MAXV, int STRIDE, typename Dep>
 SP_HD inline bool sweep3(Poly3<T, MAXV, STRIDE> &P, const Local<T> &L, int sb, int sc, Dep &dep, int ry, int *fail)
 {
     const int sx = L.span[0], sy = L.span[1], sz = L.span[2];
-    for (int ix = sb; ix < sb + sc; ++ix) {
-        int ylo = 0, yhi = -1;
-        const int ystart = ix == sb ? ry : 0;
-        for (int iy = 0;; ++iy) {
-            fail[0] = ix;
-            fail[1] = yhi < 0 ? ystart : iy;
-            fail[2] = 0;
-            // (re)build the slab ix of the simplex
+    int ix = sb;
+    int iy = -1;          // -1: the slab's column range is not known yet
+    int ylo = 0, yhi = -1;
+    int iz = 0, zhi = -1; // zhi < iz: no column in progress
+    int cx = sb, cy = 0;  // the column being swept
+    const int send = sb + sc;
+    fail[0] = ix;
+    fail[1] = ry;
+    fail[2] = 0;
+    for (;;) {
+        // build the next non-empty column
+        while (iz > zhi && ix < send) {
             P.init_tet(L.v);
             if (ix > 0 && !P.clip(0, (T)ix, true)) return false;
             if (ix < sx - 1 && !P.clip(0, (T)(ix + 1), false)) return false;
-            if (P.n == 0) break;
-            if (yhi < 0) {
-                T mn = P.coord(0, 1), mx = mn;
-                for (int v = 1; v < P.n; ++v) {
-                    T c = P.coord(v, 1);
-                    mn = c < mn ? c : mn;
-                    mx = c > mx ? c : mx;
-                }
+            if (!P.empty() && iy < 0) {
+                T mn, mx;
+                P.range(1, mn, mx);
                 ylo = (int)floor(mn);
                 yhi = (int)floor(mx);
                 ylo = ylo < 0 ? 0 : ylo;
                 yhi = yhi > sy - 1 ? sy - 1 : yhi;
-                iy = ylo > ystart ? ylo : ystart;
+                iy = ylo;
+                if (ix == sb && ry > iy) iy = ry;
             }
-            if (iy > yhi) break;
-            fail[1] = iy;
-            if (iy > ylo && !P.clip(1, (T)iy, true)) return false;
-            if (iy < yhi && !P.clip(1, (T)(iy + 1), false)) return false;
-            if (P.n == 0) {
-                if (iy >= yhi) break;
+            if (P.empty() || iy > yhi) {
+                ++ix;
+                iy = -1;
+                fail[0] = ix;
+                fail[1] = 0;
+                fail[2] = 0;
                 continue;
             }
-            T mn = P.coord(0, 2), mx = mn;
-            for (int v = 1; v < P.n; ++v) {
-                T c = P.coord(v, 2);
-                mn = c < mn ? c : mn;
-                mx = c > mx ? c : mx;
+            fail[0] = ix;
+            fail[1] = iy;
+            fail[2] = 0;
+            if (iy > ylo && !P.clip(1, (T)iy, true)) return false;
+            if (iy < yhi && !P.clip(1, (T)(iy + 1), false)) return false;
+            if (!P.empty()) {
+                T mn, mx;
+                P.range(2, mn, mx);
+                iz = (int)floor(mn);
+                zhi = (int)floor(mx);
+                iz = iz < 0 ? 0 : iz;
+                zhi = zhi > sz - 1 ? sz - 1 : zhi;
+                cx = ix;
+                cy = iy;
             }
-            int zlo = (int)floor(mn), zhi = (int)floor(mx);
-            zlo = zlo < 0 ? 0 : zlo;
-            zhi = zhi > sz - 1 ? sz - 1 : zhi;
-            for (int iz = zlo; iz <= zhi; ++iz) {
-                T s6, s24;
-                bool last = iz == zhi;
-                fail[2] = iz;
-                if (!P.integrate_below(2, (T)(iz + 1), last, s6, s24)) return false;
-                if (s24 != T(0)) dep(ix, iy, iz, s24 / T(24));
-                if (!last) {
-                    fail[2] = iz + 1;
-                    if (!P.clip(2, (T)(iz + 1), true)) return false;
-                    if (P.n == 0) break;
-                }
+            // next column (or slab) for the following build
+            if (iy >= yhi) {
+                ++ix;
+                iy = -1;
+            } else {
+                ++iy;
             }
-            if (iy >= yhi) break;
+        }
+        if (iz > zhi) break;  // nothing left
+        // one piece: the part of the column below z = iz + 1
+        T s6, s24;
+        const bool last = iz == zhi;
+        fail[0] = cx;
+        fail[1] = cy;
+        fail[2] = iz;
+        if (!P.integrate_below(2, (T)(iz + 1), last, s6, s24)) return false;
+        if (s24 != T(0)) dep(cx, cy, iz, s24 / T(24));
+        if (!last) {
+            fail[2] = iz + 1;
+            if (!P.clip(2, (T)(iz + 1), true)) return false;
+            ++iz;
+            if (P.empty()) zhi = iz - 1;
+        } else {
+            ++iz;
         }
     }
     return true;

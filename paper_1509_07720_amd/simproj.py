@@ -58,7 +58,7 @@ class sp_profile(ctypes.Structure):
     _fields_ = [("calls", ctypes.c_int), ("ms_call", ctypes.c_double), ("ms_fill", ctypes.c_double),
                 ("ms_setup", ctypes.c_double), ("ms_bin", ctypes.c_double), ("ms_clip", ctypes.c_double),
                 ("ms_clip_retry", ctypes.c_double), ("ms_finalize", ctypes.c_double),
-                ("pieces", ctypes.c_longlong), ("items", ctypes.c_longlong)]
+                ("pieces", ctypes.c_longlong), ("items", ctypes.c_longlong), ("clip_blocks", ctypes.c_int)]
 
 
 if not os.path.exists(LIB_PATH):
