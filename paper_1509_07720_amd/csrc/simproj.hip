@@ -205,12 +205,12 @@ __device__ inline DepF32 make_dep<float>(const ProbDev<float> &p, const Local<fl
     DepF32 d;
     d.hi = p.out;
     d.lo = p.lo;
-    const size_t st[3] = {1, (size_t)p.g.dims[0], (size_t)p.g.dims[0] * (size_t)p.g.dims[1]};
+    const size_t s1 = (size_t)p.g.dims[0], s2 = (size_t)p.g.dims[0] * (size_t)p.g.dims[1];
     for (int k = 0; k < 3; ++k) {
         d.anchor[k] = L.anchor[k];
-        d.dims[k] = p.g.dims[o.ax[k]];
-        d.periodic[k] = p.g.periodic[o.ax[k]];
-        d.stride[k] = st[o.ax[k]];
+        d.dims[k] = sel3(p.g.dims[0], p.g.dims[1], p.g.dims[2], o.ax[k]);
+        d.periodic[k] = sel3(p.g.periodic[0], p.g.periodic[1], p.g.periodic[2], o.ax[k]);
+        d.stride[k] = sel3((size_t)1, s1, s2, o.ax[k]);
     }
     d.scale = (float)p.g.out_scale;
     d.suppress_ix = -1;
@@ -224,12 +224,12 @@ __device__ inline DepF64 make_dep<double>(const ProbDev<double> &p, const Local<
 {
     DepF64 d;
     d.out = p.out;
-    const size_t st[3] = {1, (size_t)p.g.dims[0], (size_t)p.g.dims[0] * (size_t)p.g.dims[1]};
+    const size_t s1 = (size_t)p.g.dims[0], s2 = (size_t)p.g.dims[0] * (size_t)p.g.dims[1];
     for (int k = 0; k < 3; ++k) {
         d.anchor[k] = L.anchor[k];
-        d.dims[k] = p.g.dims[o.ax[k]];
-        d.periodic[k] = p.g.periodic[o.ax[k]];
-        d.stride[k] = st[o.ax[k]];
+        d.dims[k] = sel3(p.g.dims[0], p.g.dims[1], p.g.dims[2], o.ax[k]);
+        d.periodic[k] = sel3(p.g.periodic[0], p.g.periodic[1], p.g.periodic[2], o.ax[k]);
+        d.stride[k] = sel3((size_t)1, s1, s2, o.ax[k]);
     }
     d.scale = p.g.out_scale;
     d.suppress_ix = -1;
@@ -306,7 +306,8 @@ __global__ __launch_bounds__(256) void k_setup(ProbDev<T> p)
                 dep(0, 0, 0, val);
                 if (p.count_pieces) atomicAdd(&p.cs->pieces, 1ull);
             } else {
-                int sx = D == 3 ? L.span[sweep_order(L).ax[0]] : L.span[0];
+                const int a0 = sweep_order(L).ax[0];
+                int sx = D == 3 ? sel3(L.span[0], L.span[1], L.span[2], a0) : L.span[0];
                 int G = p.slab_group;
                 int nit = (sx + G - 1) / G;
                 if (nit > 1) {
@@ -375,88 +376,129 @@ __global__ __launch_bounds__(256) void k_scatter(ProbDev<T> p)
     }
 }
 
-// The clip kernel: persistent waves take 64 items at a time from the class-
-// ordered list (most expensive first), one item per lane.
+// The clip kernel.  Persistent one-wave blocks; each wave takes 64 items at
+// a time from the class-ordered list (most expensive first) into an LDS
+// queue, and every lane pulls its next item from that queue the moment it
+// finishes the previous one, so lanes do not wait for the slowest item of a
+// chunk.  Per loop iteration a busy lane performs one sweep step (a column
+// build if due, then one piece).
 template <int D, typename T, int MAXV>
 __global__ __launch_bounds__(WG) void k_clip(ProbDev<T> p, int overflow_pass)
 {
     constexpr int SLOTS = D == 3 ? MAXV : 2 * MAXP2;
     __shared__ V4<T> s_p[SLOTS][WG];
     __shared__ uint32_t s_nb[D == 3 ? MAXV : 1][WG];
+    __shared__ unsigned s_base, s_qn, s_qh;
+    __shared__ int s_done;
     const int lane = threadIdx.x;
-    __shared__ unsigned s_base;
-    unsigned total = overflow_pass ? min(p.cs->ovf_count, (unsigned)OVF_CAP) : p.cs->total;
+    const unsigned total = overflow_pass ? min(p.cs->ovf_count, (unsigned)OVF_CAP) : p.cs->total;
     unsigned *head = overflow_pass ? &p.cs->ovf_head : &p.cs->head;
+    if (lane == 0) {
+        s_qn = 0u;
+        s_qh = 0u;
+        s_done = 0;
+        s_base = 0u;
+    }
+    Poly3<T, MAXV, WG> P3;
+    P3.p = &s_p[0][lane];
+    P3.nb = &s_nb[0][lane];
+    P3.live = 0u;
+    Poly2<T, MAXP2, WG> P2;
+    P2.a = &s_p[0][lane];
+    P2.b = &s_p[D == 3 ? 0 : MAXP2][lane];
+    P2.n = 0;
+    bool busy = false;
+    Local<T> L;
+    typename DepFor<T>::type dep;
+    Sweep3 S;
+    int64_t sid = 0;
+    int sb = 0, sc = 0;
     for (;;) {
-        if (lane == 0) s_base = atomicAdd(head, (unsigned)WG);
-        __syncthreads();
-        unsigned base = s_base;
-        __syncthreads();
-        if (base >= total) break;
-        unsigned it = base + lane;
-        if (it < total) {
-            int64_t s;
-            int sb, sc, ry = 0, rz = 0;
-            if (overflow_pass) {
-                Ovf o = p.ovf[it];
-                s = o.s;
-                sb = o.ix;
-                sc = o.end - o.ix;
-                ry = o.iy;
-                rz = o.iz;
-            } else {
-                uint64_t item = p.items[it];
-                s = (int64_t)(uint32_t)item;
-                sb = (int)((item >> 32) & 0xffffu);
-                sc = (int)(item >> 48);
-            }
-            Local<T> L0;
-            if (setup_any<D>(p, s, false, L0) == SETUP_OK) {
-                const SweepOrder ord = D == 3 ? sweep_order(L0) : kIdentity;
-                const Local<T> L = D == 3 ? permuted(L0, ord) : L0;
-                auto dep = make_dep<T>(p, L, ord);
-                if (overflow_pass) {
-                    dep.suppress_ix = sb;
-                    dep.suppress_iy = ry;
-                    dep.suppress_iz = rz;
-                }
-                int fail[3];
-                bool ok;
-                if constexpr (D == 3) {
-                    Poly3<T, MAXV, WG> P;
-                    P.p = &s_p[0][lane];
-                    P.nb = &s_nb[0][lane];
-                    P.live = 0u;
-                    ok = sweep3(P, L, sb, sc, dep, ry, fail);
+        const int any_idle = __syncthreads_or(!busy);
+        if (any_idle && s_qh >= s_qn && !s_done) {
+            if (lane == 0) s_base = atomicAdd(head, (unsigned)WG);
+            __syncthreads();
+            if (lane == 0) {
+                if (s_base >= total) {
+                    s_done = 1;
                 } else {
-                    Poly2<T, MAXP2, WG> P;
-                    P.a = &s_p[0][lane];
-                    P.b = &s_p[MAXP2][lane];
-                    P.n = 0;
-                    ok = sweep2(P, L, sb, sc, dep, fail);
+                    s_qn = min((unsigned)WG, total - s_base);
+                    s_qh = 0u;
                 }
-                if (p.count_pieces && dep.count) atomicAdd(&p.cs->pieces, (unsigned long long)dep.count);  // counting runs only
-                if (!ok) {
-                    if (!overflow_pass) {
-                        unsigned k = atomicAdd(&p.cs->ovf_count, 1u);
-                        if (k < OVF_CAP) {
-                            Ovf o;
-                            o.s = (int)s;
-                            o.ix = fail[0];
-                            o.iy = fail[1];
-                            o.iz = fail[2];
-                            o.end = sb + sc;
-                            p.ovf[k] = o;
-                            atomicAdd(&p.es->n_overflow, 1);
-                        } else {
-                            record_error(p.es, SP_E_INTERNAL);
-                            atomicAdd(&p.es->n_internal, 1);
-                        }
-                    } else {
-                        record_error(p.es, SP_E_INTERNAL);
-                        atomicAdd(&p.es->n_internal, 1);
+            }
+            __syncthreads();
+        }
+        if (!busy && s_qh < s_qn) {
+            const unsigned k = atomicAdd(&s_qh, 1u);
+            if (k < s_qn) {
+                const unsigned it = s_base + k;
+                int ry = 0, rz = 0;
+                if (overflow_pass) {
+                    Ovf o = p.ovf[it];
+                    sid = o.s;
+                    sb = o.ix;
+                    sc = o.end - o.ix;
+                    ry = o.iy;
+                    rz = o.iz;
+                } else {
+                    uint64_t item = p.items[it];
+                    sid = (int64_t)(uint32_t)item;
+                    sb = (int)((item >> 32) & 0xffffu);
+                    sc = (int)(item >> 48);
+                }
+                Local<T> L0;
+                if (setup_any<D>(p, sid, false, L0) == SETUP_OK) {
+                    const SweepOrder ord = D == 3 ? sweep_order(L0) : kIdentity;
+                    L = D == 3 ? permuted(L0, ord) : L0;
+                    dep = make_dep<T>(p, L, ord);
+                    if (overflow_pass) {
+                        dep.suppress_ix = sb;
+                        dep.suppress_iy = ry;
+                        dep.suppress_iz = rz;
                     }
+                    S.start(sb, sc, ry);
+                    busy = true;
                 }
+            }
+        }
+        const int any_busy = __syncthreads_or(busy);
+        if (!any_busy) {
+            if (s_done) break;
+            continue;
+        }
+        if (!busy) continue;
+        int r;
+        if constexpr (D == 3) {
+            r = S.step(P3, L, dep);
+        } else {
+            int fail2[3];
+            r = sweep2(P2, L, sb, sc, dep, fail2) ? 0 : -1;
+            S.fail[0] = fail2[0];
+            S.fail[1] = fail2[1];
+            S.fail[2] = fail2[2];
+        }
+        if (r > 0) continue;
+        busy = false;
+        if (p.count_pieces && dep.count) atomicAdd(&p.cs->pieces, (unsigned long long)dep.count);  // counting runs only
+        if (r < 0) {
+            if (!overflow_pass) {
+                unsigned k = atomicAdd(&p.cs->ovf_count, 1u);
+                if (k < OVF_CAP) {
+                    Ovf o;
+                    o.s = (int)sid;
+                    o.ix = S.fail[0];
+                    o.iy = S.fail[1];
+                    o.iz = S.fail[2];
+                    o.end = sb + sc;
+                    p.ovf[k] = o;
+                    atomicAdd(&p.es->n_overflow, 1);
+                } else {
+                    record_error(p.es, SP_E_INTERNAL);
+                    atomicAdd(&p.es->n_internal, 1);
+                }
+            } else {
+                record_error(p.es, SP_E_INTERNAL);
+                atomicAdd(&p.es->n_internal, 1);
             }
         }
     }

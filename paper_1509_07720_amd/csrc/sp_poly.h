@@ -172,26 +172,28 @@ struct Poly3 {
             live = 0u;
             return true;
         }
+        const uint32_t gone = live & ~keep;
         uint32_t freem = ~live & SLOTS;
         uint32_t fresh = 0u;
-        for (uint32_t w = keep; w; w &= w - 1u) {
-            const int v = lowbit(w);
-            uint32_t nbv = N(v);
-            const uint32_t nb0 = nbv;
-            const V4<T> pv = P(v);
+        // one new vertex per edge between a removed and a kept vertex; the
+        // removed side is usually the smaller one (the piece being cut off)
+        for (uint32_t w = gone; w; w &= w - 1u) {
+            const int x = lowbit(w);
+            const uint32_t nbx = N(x);
+            const V4<T> px = P(x);
             for (int i = 0; i < 3; ++i) {
-                int x = nbr(nb0, i);
-                if ((keep >> x) & 1u) continue;
+                const int v = nbr(nbx, i);
+                if (!((keep >> v) & 1u)) continue;
                 if (freem == 0u) return false;
                 const int u = lowbit(freem);
                 freem &= freem - 1u;
                 fresh |= 1u << u;
-                const V4<T> px = P(x);
+                const V4<T> pv = P(v);
                 setP(u, keep_upper ? isect(px, pv, ax, c) : isect(pv, px, ax, c));
                 setN(u, pack3(v, v, v));
-                nbv = set_nbr(nbv, i, u);
+                const uint32_t nbv = N(v);
+                setN(v, set_nbr(nbv, slot_of(nbv, x), u));
             }
-            if (nbv != nb0) setN(v, nbv);
         }
         // link the new vertices around the cap: from each one, walk its
         // facet through kept vertices to the next new vertex.  One flat loop
@@ -254,6 +256,8 @@ struct Poly3 {
                 }
             }
         }
+        // only facets holding a vertex below the plane contribute; each is
+        // reached from a directed edge leaving one of its below vertices
         uint32_t un0 = live, un1 = live, un2 = live;
         int vs = 0, vcur = 0, pc = 0, cnt = 0;
         bool open = false, ba = false;
@@ -283,8 +287,8 @@ struct Poly3 {
         const int steps = 3 * __builtin_popcount(live);
         for (int it = 0; it < steps; ++it) {
             if (!open) {
-                const uint32_t any = un0 | un1 | un2;
-                if (any == 0u) return false;
+                const uint32_t any = (un0 | un1 | un2) & below;
+                if (any == 0u) return true;
                 const int v = lowbit(any);
                 pc = ((un0 >> v) & 1u) ? 0 : (((un1 >> v) & 1u) ? 1 : 2);
                 vs = v;
@@ -313,7 +317,7 @@ struct Poly3 {
                 ba = bb;
             }
         }
-        return !open;
+        return !open && ((un0 | un1 | un2) & below) == 0u;
     }
 };
 

@@ -277,16 +277,25 @@ struct SweepOrder {
 template <typename T>
 SP_HD inline SweepOrder sweep_order(const Local<T> &L)
 {
+    // sort axes by span, ascending; ties keep x, y, z order (written with
+    // compares on values only, so nothing is indexed at run time)
+    const int s0 = L.span[0], s1 = L.span[1], s2 = L.span[2];
+    const bool l01 = s1 < s0, l02 = s2 < s0, l12 = s2 < s1;
+    const int r0 = (int)l01 + (int)l02;            // rank of axis 0
+    const int r1 = (int)!l01 + (int)l12;           // rank of axis 1
     SweepOrder o;
-    int a = 0, b = 1, c = 2;
-    // sort axes by span, ascending; ties keep x, y, z order
-    if (L.span[b] < L.span[a]) { int t = a; a = b; b = t; }
-    if (L.span[c] < L.span[b]) { int t = b; b = c; c = t; }
-    if (L.span[b] < L.span[a]) { int t = a; a = b; b = t; }
-    o.ax[0] = a;
-    o.ax[1] = b;
-    o.ax[2] = c;
+    o.ax[0] = r0 == 0 ? 0 : (r1 == 0 ? 1 : 2);
+    o.ax[1] = r0 == 1 ? 0 : (r1 == 1 ? 1 : 2);
+    o.ax[2] = r0 == 2 ? 0 : (r1 == 2 ? 1 : 2);
     return o;
+}
+
+// One of three values by a run-time index, as selects (a register array
+// indexed at run time would go to scratch memory).
+template <typename X>
+SP_HD inline X sel3(const X &a, const X &b, const X &c, int i)
+{
+    return i == 0 ? a : (i == 1 ? b : c);
 }
 
 // The simplex with its axes relabelled so that sweep axis k becomes local
@@ -296,14 +305,13 @@ SP_HD inline Local<T> permuted(const Local<T> &L, const SweepOrder &o)
 {
     Local<T> M = L;
     for (int k = 0; k < 4; ++k) {
-        const T c[3] = {L.v[k].x, L.v[k].y, L.v[k].z};
-        M.v[k].x = c[o.ax[0]];
-        M.v[k].y = c[o.ax[1]];
-        M.v[k].z = c[o.ax[2]];
+        M.v[k].x = sel3(L.v[k].x, L.v[k].y, L.v[k].z, o.ax[0]);
+        M.v[k].y = sel3(L.v[k].x, L.v[k].y, L.v[k].z, o.ax[1]);
+        M.v[k].z = sel3(L.v[k].x, L.v[k].y, L.v[k].z, o.ax[2]);
     }
     for (int d = 0; d < 3; ++d) {
-        M.span[d] = L.span[o.ax[d]];
-        M.anchor[d] = L.anchor[o.ax[d]];
+        M.span[d] = sel3(L.span[0], L.span[1], L.span[2], o.ax[d]);
+        M.anchor[d] = sel3(L.anchor[0], L.anchor[1], L.anchor[2], o.ax[d]);
     }
     // a transposition of two axes flips the orientation; the three cyclic
     // orders keep it
@@ -317,35 +325,51 @@ SP_HD inline Local<T> permuted(const Local<T> &L, const SweepOrder &o)
 }
 
 // Sweep of one 3D simplex over the slabs [sb, sb+sc) of its outermost axis,
-// starting at column ry of the first slab.  dep(i0, i1, i2, value) receives
-// each piece's integral of rho in cell-volume units (local cell indices
-// along the sweep axes).
+// starting at column ry of the first slab.  The deposit receives each
+// piece's integral of rho in cell-volume units at its local cell indices
+// along the sweep axes.
 //
-// The sweep is one flat loop whose every step first builds the next column
-// polytope if the previous one is finished (the simplex cut by the planes of
-// slab i0 and column i1) and then cuts off and integrates one piece, so that
-// the lanes of a wave advance together whatever their slab, column and cell
-// counts.  Returns false when a polytope exceeds its capacity; fail =
-// (i0, i1, i2) is then the first piece not yet deposited, in sweep order.
-template <typename T, int MAXV, int STRIDE, typename Dep>
-SP_HD inline bool sweep3(Poly3<T, MAXV, STRIDE> &P, const Local<T> &L, int sb, int sc, Dep &dep, int ry, int *fail)
-{
-    const int sx = L.span[0], sy = L.span[1], sz = L.span[2];
-    int ix = sb;
-    int iy = -1;          // -1: the slab's column range is not known yet
-    int ylo = 0, yhi = -1;
-    int iz = 0, zhi = -1; // zhi < iz: no column in progress
-    int cx = sb, cy = 0;  // the column being swept
-    const int send = sb + sc;
-    fail[0] = ix;
-    fail[1] = ry;
-    fail[2] = 0;
-    for (;;) {
+// The sweep is resumable: step() first builds the next column polytope if
+// the previous one is finished (the simplex cut by the planes of slab i0 and
+// column i1) and then cuts off and integrates one piece.  A GPU lane calls
+// step() once per loop iteration and takes a new simplex as soon as its
+// current one is done, so the lanes of a wave stay busy whatever their
+// slab, column and cell counts.  On a capacity failure, fail = (i0, i1, i2)
+// is the first piece not yet deposited, in sweep order.
+struct Sweep3 {
+    int sb, send, ry;
+    int ix, iy, ylo, yhi, iz, zhi, cx, cy;
+    int fail[3];
+
+    SP_HD void start(int sb_, int sc_, int ry_)
+    {
+        sb = sb_;
+        send = sb_ + sc_;
+        ry = ry_;
+        ix = sb;
+        iy = -1;
+        ylo = 0;
+        yhi = -1;
+        iz = 0;
+        zhi = -1;
+        cx = sb;
+        cy = 0;
+        fail[0] = ix;
+        fail[1] = ry;
+        fail[2] = 0;
+    }
+
+    // One step.  Returns 1 when a piece was processed and more may follow,
+    // 0 when the sweep is finished, -1 on a capacity failure.
+    template <typename T, int MAXV, int STRIDE, typename Dep>
+    SP_HD int step(Poly3<T, MAXV, STRIDE> &P, const Local<T> &L, Dep &dep)
+    {
+        const int sx = L.span[0], sy = L.span[1], sz = L.span[2];
         // build the next non-empty column
         while (iz > zhi && ix < send) {
             P.init_tet(L.v);
-            if (ix > 0 && !P.clip(0, (T)ix, true)) return false;
-            if (ix < sx - 1 && !P.clip(0, (T)(ix + 1), false)) return false;
+            if (ix > 0 && !P.clip(0, (T)ix, true)) return -1;
+            if (ix < sx - 1 && !P.clip(0, (T)(ix + 1), false)) return -1;
             if (!P.empty() && iy < 0) {
                 T mn, mx;
                 P.range(1, mn, mx);
@@ -367,8 +391,8 @@ SP_HD inline bool sweep3(Poly3<T, MAXV, STRIDE> &P, const Local<T> &L, int sb, i
             fail[0] = ix;
             fail[1] = iy;
             fail[2] = 0;
-            if (iy > ylo && !P.clip(1, (T)iy, true)) return false;
-            if (iy < yhi && !P.clip(1, (T)(iy + 1), false)) return false;
+            if (iy > ylo && !P.clip(1, (T)iy, true)) return -1;
+            if (iy < yhi && !P.clip(1, (T)(iy + 1), false)) return -1;
             if (!P.empty()) {
                 T mn, mx;
                 P.range(2, mn, mx);
@@ -387,25 +411,40 @@ SP_HD inline bool sweep3(Poly3<T, MAXV, STRIDE> &P, const Local<T> &L, int sb, i
                 ++iy;
             }
         }
-        if (iz > zhi) break;  // nothing left
+        if (iz > zhi) return 0;  // nothing left
         // one piece: the part of the column below z = iz + 1
         T s6, s24;
         const bool last = iz == zhi;
         fail[0] = cx;
         fail[1] = cy;
         fail[2] = iz;
-        if (!P.integrate_below(2, (T)(iz + 1), last, s6, s24)) return false;
+        if (!P.integrate_below(2, (T)(iz + 1), last, s6, s24)) return -1;
         if (s24 != T(0)) dep(cx, cy, iz, s24 / T(24));
         if (!last) {
             fail[2] = iz + 1;
-            if (!P.clip(2, (T)(iz + 1), true)) return false;
+            if (!P.clip(2, (T)(iz + 1), true)) return -1;
             ++iz;
             if (P.empty()) zhi = iz - 1;
         } else {
             ++iz;
         }
+        return 1;
     }
-    return true;
+};
+
+// The whole sweep of one simplex in one call (host-side tools and tests).
+template <typename T, int MAXV, int STRIDE, typename Dep>
+SP_HD inline bool sweep3(Poly3<T, MAXV, STRIDE> &P, const Local<T> &L, int sb, int sc, Dep &dep, int ry, int *fail)
+{
+    Sweep3 S;
+    S.start(sb, sc, ry);
+    int r;
+    while ((r = S.step(P, L, dep)) > 0) {
+    }
+    fail[0] = S.fail[0];
+    fail[1] = S.fail[1];
+    fail[2] = S.fail[2];
+    return r == 0;
 }
 
 // Convex polygon (2D pieces): an ordered, counter-clockwise vertex list in two
