@@ -36,7 +36,7 @@ namespace {
 
 constexpr int WG = 64;       // lanes per block in the clip kernels (one wave)
 constexpr int NCLS = 16;     // cost classes
-constexpr int MAXV3 = 24;    // polytope vertex slots per lane (measured peak 22)
+constexpr int MAXV3 = 18;    // polytope vertex slots per lane (no overflow measured at 18)
 constexpr int MAXV3_BIG = 32;
 constexpr int MAXP2 = 12;    // polygon vertices per lane and buffer (peak 8)
 constexpr int OVF_CAP = 1 << 16;

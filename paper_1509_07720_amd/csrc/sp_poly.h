@@ -176,24 +176,38 @@ struct Poly3 {
         uint32_t freem = ~live & SLOTS;
         uint32_t fresh = 0u;
         // one new vertex per edge between a removed and a kept vertex; the
-        // removed side is usually the smaller one (the piece being cut off)
+        // removed side is usually the smaller one (the piece being cut off).
+        // A removed vertex is dead once its own edges are done (its position
+        // and neighbours are held in registers and no kept vertex refers to
+        // it any more), so its slot takes its first new vertex -- the kept
+        // neighbour's list then needs no edit -- or returns to the free pool.
         for (uint32_t w = gone; w; w &= w - 1u) {
             const int x = lowbit(w);
             const uint32_t nbx = N(x);
             const V4<T> px = P(x);
+            bool reused = false;
             for (int i = 0; i < 3; ++i) {
                 const int v = nbr(nbx, i);
                 if (!((keep >> v) & 1u)) continue;
-                if (freem == 0u) return false;
-                const int u = lowbit(freem);
-                freem &= freem - 1u;
+                int u;
+                if (!reused) {
+                    u = x;
+                    reused = true;
+                } else {
+                    if (freem == 0u) return false;
+                    u = lowbit(freem);
+                    freem &= freem - 1u;
+                }
                 fresh |= 1u << u;
                 const V4<T> pv = P(v);
                 setP(u, keep_upper ? isect(px, pv, ax, c) : isect(pv, px, ax, c));
                 setN(u, pack3(v, v, v));
-                const uint32_t nbv = N(v);
-                setN(v, set_nbr(nbv, slot_of(nbv, x), u));
+                if (u != x) {
+                    const uint32_t nbv = N(v);
+                    setN(v, set_nbr(nbv, slot_of(nbv, x), u));
+                }
             }
+            if (!reused) freem |= 1u << x;
         }
         // link the new vertices around the cap: from each one, walk its
         // facet through kept vertices to the next new vertex.  One flat loop
