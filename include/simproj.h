@@ -123,22 +123,48 @@ sp_status sp_project_tets(sp_ctx *ctx, const sp_problem *prob, sp_precision prec
  * paper's 2D, i.e. 4D phase-space, case; Section 3.1 eq. eq:E02D). */
 sp_status sp_project_tris(sp_ctx *ctx, const sp_problem *prob, sp_precision prec, void *stream);
 
-/* Project n independent problems of dimension `dim` (3 only in this build)
- * in one persistent, work-stealing launch; `probs` is a HOST array of n
- * problems whose buffers are device pointers.  Equivalent to n calls of
- * sp_project_tets, with the load balanced across all of them (the
- * cost-based balancing the paper proposes in Section 7). */
+/* Project n independent problems of dimension `dim` (3 only in this build;
+ * 1 <= n <= 65535, n == 0 is a no-op) in one persistent, work-stealing
+ * launch; `probs` is a HOST array of n problems whose buffers are device
+ * pointers, each problem as in sp_project_tets (flags, out_lo and
+ * total_mass per problem; their output grids must not overlap).  The work
+ * items of all problems are ordered by estimated cost in one list, so the
+ * load is balanced across problems (the cost-based balancing the paper
+ * proposes for its future work, Section 7).  The launch sequence is captured
+ * once per signature (the sp_problem bytes, precision, tuning and scratch
+ * buffer) into a HIP graph and replayed on `stream` by later calls with the
+ * same signature; the context keeps at most 16 such graphs.  The first call
+ * of a signature synchronises with the device (graph capture, descriptor
+ * upload); the others only enqueue.  Stage times of sp_profile are not
+ * split for batches (ms_call only). */
 sp_status sp_project_batch(sp_ctx *ctx, int dim, const sp_problem *probs, int n, sp_precision prec, void *stream);
 
 /* Wait for `stream`, then report the first device-side error recorded since
  * the previous call (SP_VALIDATE checks, capacity failures) and clear it. */
 sp_status sp_sync_status(sp_ctx *ctx, void *stream);
 
-/* Time the tunable launch parameters on the given sample problems and keep
- * the fastest for subsequent calls; when cache_path is not NULL, read the
- * result from that file if present, else write it there.  Synchronous. */
+/* Time the tunable launch parameters (the x-slab group of a work item and
+ * the clip blocks per CU) on the n sample problems of dimension `dim` and
+ * keep the fastest for subsequent calls of this context.  Project-written
+ * search: every candidate pair is run once to warm up and then timed twice
+ * with HIP events, the sample projected one problem after another; the
+ * sample's output grids are overwritten.  When cache_path is not NULL the
+ * text file is searched first for a line with the sample's signature (its
+ * sizes, grid descriptions, precision and CU count, not its pointers); if
+ * found, its parameters are applied without timing, else the result is
+ * appended to the file (SP_E_INVALID_ARG if it cannot be written; the result
+ * is applied anyway).  Synchronous. */
 sp_status sp_autotune(sp_ctx *ctx, int dim, const sp_problem *sample, int n, sp_precision prec,
                       const char *cache_path);
+
+/* The launch parameters in use: x-slabs per work item and clip blocks per
+ * CU (0: as many as fit on a CU).  Either pointer may be NULL. */
+sp_status sp_tuning_read(sp_ctx *ctx, int *slab_group, int *blocks_per_cu);
+
+/* Set the launch parameters by hand (slab_group in 1..4095, blocks_per_cu
+ * in 0..64, else SP_E_INVALID_ARG); they hold for later calls of this
+ * context until changed or retuned.  Results do not depend on them. */
+sp_status sp_tuning_set(sp_ctx *ctx, int slab_group, int blocks_per_cu);
 
 /* Per-stage device times of the projection calls made while profiling is
  * on, from HIP events recorded on each call's own stream around its kernels

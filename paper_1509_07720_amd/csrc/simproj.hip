@@ -65,7 +65,7 @@ struct ErrState {
 };
 
 struct Ovf {
-    int s, ix, iy, iz, end;
+    int s, ix, iy, iz, end, pid;
 };
 
 struct Tuning {
@@ -173,8 +173,9 @@ struct ProbDev {
     GridDev g;
     T *out;        // hi (FP32C) or the grid (FP64)
     float *lo;     // FP32C low grid
-    uint32_t *tinfo;
-    uint64_t *items;
+    uint32_t *tinfo;        // this problem's slice
+    uint64_t *items;        // shared by all problems of a launch
+    uint16_t *item_prob;    // problem of each item (batches only)
     unsigned extra_cap;
     Ovf *ovf;
     CallState *cs;
@@ -182,6 +183,37 @@ struct ProbDev {
     int slab_group;
     int count_pieces;
 };
+
+// Several problems in one launch: their descriptors in device memory and
+// the running totals of their simplex counts (offs[nprob] = all simplices).
+// nprob == 0 means a single problem passed by value.
+struct Batch {
+    const void *probs;
+    const int64_t *offs;
+    int nprob;
+    int64_t ntotal;
+};
+
+// Problem and local simplex index of a flat simplex index.
+template <typename T>
+__device__ inline void locate(const ProbDev<T> &p0, const Batch &b, int64_t g, ProbDev<T> &p, int64_t &s, int &pi)
+{
+    if (b.nprob == 0) {
+        p = p0;
+        s = g;
+        pi = 0;
+        return;
+    }
+    int lo = 0, hi = b.nprob - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (b.offs[mid] <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    pi = lo;
+    p = static_cast<const ProbDev<T> *>(b.probs)[lo];
+    s = g - b.offs[lo];
+}
 
 template <int D>
 __device__ inline int setup_any(const ProbDev<float> &p, int64_t s, bool validate, Local<float> &L)
@@ -287,13 +319,18 @@ __global__ void k_clear_state(CallState *cs, double *total)
 }
 
 template <int D, typename T>
-__global__ __launch_bounds__(256) void k_setup(ProbDev<T> p)
+__global__ __launch_bounds__(256) void k_setup(ProbDev<T> p0, Batch b)
 {
     __shared__ unsigned s_hist[NCLS];
     if (threadIdx.x < NCLS) s_hist[threadIdx.x] = 0u;
     __syncthreads();
-    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s < p.n) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t ntotal = b.nprob ? b.ntotal : p0.n;
+    if (g < ntotal) {
+        ProbDev<T> p;
+        int64_t s;
+        int pi;
+        locate(p0, b, g, p, s, pi);
         Local<T> L;
         int st = setup_any<D>(p, s, p.validate != 0, L);
         uint32_t info = 0u;
@@ -310,6 +347,7 @@ __global__ __launch_bounds__(256) void k_setup(ProbDev<T> p)
                 int sx = D == 3 ? sel3(L.span[0], L.span[1], L.span[2], a0) : L.span[0];
                 int G = p.slab_group;
                 int nit = (sx + G - 1) / G;
+                if (nit > 4095) nit = 4095;  // 12-bit field of the item count
                 if (nit > 1) {
                     unsigned old = atomicAdd(&p.cs->extra, (unsigned)(nit - 1));
                     if (old + (unsigned)(nit - 1) > p.extra_cap) nit = 1;
@@ -333,7 +371,7 @@ __global__ __launch_bounds__(256) void k_setup(ProbDev<T> p)
         p.tinfo[s] = info;
     }
     __syncthreads();
-    if (threadIdx.x < NCLS && s_hist[threadIdx.x]) atomicAdd(&p.cs->hist[threadIdx.x], s_hist[threadIdx.x]);
+    if (threadIdx.x < NCLS && s_hist[threadIdx.x]) atomicAdd(&p0.cs->hist[threadIdx.x], s_hist[threadIdx.x]);
 }
 
 __global__ void k_scan(CallState *cs)
@@ -349,20 +387,28 @@ __global__ void k_scan(CallState *cs)
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_scatter(ProbDev<T> p)
+__global__ __launch_bounds__(256) void k_scatter(ProbDev<T> p0, Batch b)
 {
     __shared__ unsigned s_cnt[NCLS];
     __shared__ unsigned s_base[NCLS];
     if (threadIdx.x < NCLS) s_cnt[threadIdx.x] = 0u;
     __syncthreads();
-    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    uint32_t info = s < p.n ? p.tinfo[s] : 0u;
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t ntotal = b.nprob ? b.ntotal : p0.n;
+    ProbDev<T> p;
+    int64_t s = 0;
+    int pi = 0;
+    uint32_t info = 0u;
+    if (g < ntotal) {
+        locate(p0, b, g, p, s, pi);
+        info = p.tinfo[s];
+    }
     int cls = (int)(info >> 28), nit = (int)((info >> 16) & 0xfffu), sx = (int)(info & 0xffffu);
     unsigned local = 0;
     if (info) local = atomicAdd(&s_cnt[cls], (unsigned)nit);
     __syncthreads();
     if (threadIdx.x < NCLS && s_cnt[threadIdx.x])
-        s_base[threadIdx.x] = atomicAdd(&p.cs->cursor[threadIdx.x], s_cnt[threadIdx.x]);
+        s_base[threadIdx.x] = atomicAdd(&p0.cs->cursor[threadIdx.x], s_cnt[threadIdx.x]);
     __syncthreads();
     if (info) {
         unsigned pos = s_base[cls] + local;
@@ -371,7 +417,8 @@ __global__ __launch_bounds__(256) void k_scatter(ProbDev<T> p)
             int sb = k * per;
             int sc = sx - sb < per ? sx - sb : per;
             if (sc <= 0) sc = 0;
-            p.items[pos + k] = (uint64_t)(uint32_t)s | ((uint64_t)sb << 32) | ((uint64_t)sc << 48);
+            p0.items[pos + k] = (uint64_t)(uint32_t)s | ((uint64_t)sb << 32) | ((uint64_t)sc << 48);
+            if (b.nprob) p0.item_prob[pos + k] = (uint16_t)pi;
         }
     }
 }
@@ -383,8 +430,9 @@ __global__ __launch_bounds__(256) void k_scatter(ProbDev<T> p)
 // chunk.  Per loop iteration a busy lane performs one sweep step (a column
 // build if due, then one piece).
 template <int D, typename T, int MAXV>
-__global__ __launch_bounds__(WG) void k_clip(ProbDev<T> p, int overflow_pass)
+__global__ __launch_bounds__(WG) void k_clip(ProbDev<T> p0, Batch b, int overflow_pass)
 {
+    const ProbDev<T> &p = p0;  // fields shared by every problem of the launch
     constexpr int SLOTS = D == 3 ? MAXV : 2 * MAXP2;
     __shared__ V4<T> s_p[SLOTS][WG];
     __shared__ uint32_t s_nb[D == 3 ? MAXV : 1][WG];
@@ -412,7 +460,7 @@ __global__ __launch_bounds__(WG) void k_clip(ProbDev<T> p, int overflow_pass)
     typename DepFor<T>::type dep;
     Sweep3 S;
     int64_t sid = 0;
-    int sb = 0, sc = 0;
+    int sb = 0, sc = 0, pid = 0;
     for (;;) {
         const int any_idle = __syncthreads_or(!busy);
         if (any_idle && s_qh >= s_qn && !s_done) {
@@ -440,17 +488,20 @@ __global__ __launch_bounds__(WG) void k_clip(ProbDev<T> p, int overflow_pass)
                     sc = o.end - o.ix;
                     ry = o.iy;
                     rz = o.iz;
+                    pid = o.pid;
                 } else {
                     uint64_t item = p.items[it];
                     sid = (int64_t)(uint32_t)item;
                     sb = (int)((item >> 32) & 0xffffu);
                     sc = (int)(item >> 48);
+                    pid = b.nprob ? (int)p.item_prob[it] : 0;
                 }
+                const ProbDev<T> q = b.nprob ? static_cast<const ProbDev<T> *>(b.probs)[pid] : p0;
                 Local<T> L0;
-                if (setup_any<D>(p, sid, false, L0) == SETUP_OK) {
+                if (setup_any<D>(q, sid, false, L0) == SETUP_OK) {
                     const SweepOrder ord = D == 3 ? sweep_order(L0) : kIdentity;
                     L = D == 3 ? permuted(L0, ord) : L0;
-                    dep = make_dep<T>(p, L, ord);
+                    dep = make_dep<T>(q, L, ord);
                     if (overflow_pass) {
                         dep.suppress_ix = sb;
                         dep.suppress_iy = ry;
@@ -490,6 +541,7 @@ __global__ __launch_bounds__(WG) void k_clip(ProbDev<T> p, int overflow_pass)
                     o.iy = S.fail[1];
                     o.iz = S.fail[2];
                     o.end = sb + sc;
+                    o.pid = pid;
                     p.ovf[k] = o;
                     atomicAdd(&p.es->n_overflow, 1);
                 } else {
@@ -554,19 +606,42 @@ struct sp_ctx {
     // (start, end) events per recorded stage and per whole call
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[ST_N];
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_call;
+    // captured batched launches, by problem signature
+    hipStream_t cap_stream;
+    std::vector<struct GraphEntry> graphs;
 };
+
+struct GraphEntry {
+    uint64_t key;
+    hipGraphExec_t exec;
+    void *dev;  // problem descriptors and simplex offsets of this signature
+};
+
+static void drop_graphs(sp_ctx *ctx)
+{
+    for (GraphEntry &g : ctx->graphs) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        if (g.dev) (void)hipFree(g.dev);
+    }
+    ctx->graphs.clear();
+}
 
 // Event pair around one stage of a call (no-op unless profiling).
 struct StageTimer {
-    sp_ctx *ctx;
+    sp_ctx *ctx;  // NULL: no timing
     hipStream_t s;
     hipEvent_t a = nullptr, b = nullptr;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> *dst;
     StageTimer(sp_ctx *c, hipStream_t st, std::vector<std::pair<hipEvent_t, hipEvent_t>> *d) : ctx(c), s(st), dst(d)
     {
-        if (ctx->profiling && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess)
+        if (ctx && ctx->profiling && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess)
             (void)hipEventRecord(a, s);
     }
+    StageTimer(StageTimer &&o) noexcept : ctx(o.ctx), s(o.s), a(o.a), b(o.b), dst(o.dst)
+    {
+        o.a = o.b = nullptr;
+    }
+    StageTimer(const StageTimer &) = delete;
     ~StageTimer()
     {
         if (a && b) {
@@ -631,6 +706,11 @@ extern "C" sp_status sp_create(int hip_device, sp_ctx **ctx)
     c->profiling = 0;
     c->prof_calls = 0;
     c->last_clip_blocks = 0;
+    if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipFree(st);
+        delete c;
+        return fail(SP_E_DEVICE, "stream creation failed");
+    }
     *ctx = c;
     return SP_OK;
 }
@@ -641,6 +721,8 @@ extern "C" void sp_destroy(sp_ctx *ctx)
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
     drop_events(ctx);
+    drop_graphs(ctx);
+    (void)hipStreamDestroy(ctx->cap_stream);
     if (ctx->scratch) (void)hipFree(ctx->scratch);
     (void)hipFree(ctx->cs);
     delete ctx;
@@ -655,6 +737,7 @@ static sp_status ensure_scratch(sp_ctx *ctx, size_t bytes)
 {
     if (bytes <= ctx->scratch_cap) return SP_OK;
     HIPCHECK(hipDeviceSynchronize());
+    drop_graphs(ctx);  // captured launches refer to the old scratch
     if (ctx->scratch) (void)hipFree(ctx->scratch);
     ctx->scratch = nullptr;
     ctx->scratch_cap = 0;
@@ -729,103 +812,169 @@ static int grid_blocks(size_t n, int per)
     return (int)b;
 }
 
+// One problem of a launch: its device descriptor and the host-side facts
+// its fill and finalize steps need.
+template <typename T>
+struct Prepared {
+    ProbDev<T> p;
+    size_t ncell;
+    bool keep_lo, accumulate;
+    double to_mass;
+    double *total;
+};
+
+// Scratch layout and descriptors for a launch over n problems.
 template <int D, typename T>
-static sp_status project_impl(sp_ctx *ctx, const sp_problem *prob, sp_precision prec, hipStream_t stream)
+static sp_status prepare(sp_ctx *ctx, const sp_problem *probs, int n, std::vector<Prepared<T>> &out, int64_t &ntotal)
 {
-    sp_status st;
-    HIPCHECK(hipSetDevice(ctx->device));
-    const int64_t n = prob->n_simplex;
-    size_t ncell = 1;
-    for (int d = 0; d < D; ++d) ncell *= (size_t)prob->grid.dims[d];
     const bool fp32 = sizeof(T) == 4;
-    const bool keep_lo = fp32 && prob->out_lo != nullptr;
-    const bool accumulate = (prob->grid.flags & SP_ACCUMULATE) != 0;
-    const unsigned extra_cap = (unsigned)(n / 2 + 4096);
-    // scratch layout
+    ntotal = 0;
+    size_t lo_cells = 0;
+    for (int i = 0; i < n; ++i) {
+        ntotal += probs[i].n_simplex;
+        size_t nc = 1;
+        for (int d = 0; d < D; ++d) nc *= (size_t)probs[i].grid.dims[d];
+        if (fp32 && !probs[i].out_lo) lo_cells += nc;
+    }
+    if (ntotal >= ((int64_t)1 << 31)) return fail(SP_E_INVALID_ARG, "%lld simplices in one launch (limit 2^31)", (long long)ntotal);
+    const unsigned extra_cap = (unsigned)(ntotal / 2 + 4096);
+    const size_t nitems = (size_t)ntotal + extra_cap;
     size_t off = 0;
-    size_t o_tinfo = off;
-    off = align_up(off + sizeof(uint32_t) * (size_t)(n > 0 ? n : 1));
-    size_t o_items = off;
-    off = align_up(off + sizeof(uint64_t) * ((size_t)n + extra_cap));
-    size_t o_ovf = off;
+    const size_t o_tinfo = off;
+    off = align_up(off + sizeof(uint32_t) * (size_t)(ntotal > 0 ? ntotal : 1));
+    const size_t o_items = off;
+    off = align_up(off + sizeof(uint64_t) * nitems);
+    const size_t o_iprob = off;
+    if (n > 1) off = align_up(off + sizeof(uint16_t) * nitems);
+    const size_t o_ovf = off;
     off = align_up(off + sizeof(Ovf) * OVF_CAP);
-    size_t o_lo = off;
-    if (fp32 && !keep_lo) off = align_up(off + sizeof(float) * ncell);
-    st = ensure_scratch(ctx, off);
+    const size_t o_lo = off;
+    off = align_up(off + sizeof(float) * lo_cells);
+    sp_status st = ensure_scratch(ctx, off);
     if (st != SP_OK) return st;
     char *base = reinterpret_cast<char *>(ctx->scratch);
-
-    ProbDev<T> p;
-    p.xyz = reinterpret_cast<const T *>(prob->xyz);
-    p.n_vert = prob->n_vert;
-    p.simp = prob->simplices;
-    p.n = n;
-    p.rho = reinterpret_cast<const T *>(prob->rho);
-    p.per_corner = (prob->grid.flags & SP_RHO_PER_CORNER) != 0;
-    p.validate = (prob->grid.flags & SP_VALIDATE) != 0;
-    fill_grid<T>(p.g, prob, D);
-    p.out = reinterpret_cast<T *>(prob->out);
-    p.lo = fp32 ? (keep_lo ? prob->out_lo : reinterpret_cast<float *>(base + o_lo)) : nullptr;
-    p.tinfo = reinterpret_cast<uint32_t *>(base + o_tinfo);
-    p.items = reinterpret_cast<uint64_t *>(base + o_items);
-    p.extra_cap = extra_cap;
-    p.ovf = reinterpret_cast<Ovf *>(base + o_ovf);
-    p.cs = ctx->cs;
-    p.es = ctx->es;
-    p.slab_group = ctx->tune.slab_group;
-    p.count_pieces = ctx->profiling >= 2;
-
-    double *total = prob->total_mass;
-    if (ctx->profiling) ctx->prof_calls++;
-    StageTimer whole(ctx, stream, &ctx->ev_call);
-    {
-        StageTimer t(ctx, stream, &ctx->ev[ST_FILL]);
-        hipLaunchKernelGGL(k_clear_state, dim3(1), dim3(64), 0, stream, ctx->cs, total);
-        if (!accumulate) {
-            hipLaunchKernelGGL(k_fill<T>, dim3(grid_blocks(ncell, 256)), dim3(256), 0, stream, p.out, ncell);
+    out.resize(n);
+    int64_t toff = 0;
+    size_t loff = 0;
+    for (int i = 0; i < n; ++i) {
+        const sp_problem *prob = &probs[i];
+        Prepared<T> &q = out[i];
+        ProbDev<T> &p = q.p;
+        q.ncell = 1;
+        for (int d = 0; d < D; ++d) q.ncell *= (size_t)prob->grid.dims[d];
+        q.keep_lo = fp32 && prob->out_lo != nullptr;
+        q.accumulate = (prob->grid.flags & SP_ACCUMULATE) != 0;
+        q.total = prob->total_mass;
+        q.to_mass = 1.0;
+        if (!(prob->grid.flags & SP_OUT_MASS))
+            for (int d = 0; d < D; ++d) q.to_mass *= prob->grid.extent[d] / (double)prob->grid.dims[d];
+        p.xyz = reinterpret_cast<const T *>(prob->xyz);
+        p.n_vert = prob->n_vert;
+        p.simp = prob->simplices;
+        p.n = prob->n_simplex;
+        p.rho = reinterpret_cast<const T *>(prob->rho);
+        p.per_corner = (prob->grid.flags & SP_RHO_PER_CORNER) != 0;
+        p.validate = (prob->grid.flags & SP_VALIDATE) != 0;
+        fill_grid<T>(p.g, prob, D);
+        p.out = reinterpret_cast<T *>(prob->out);
+        p.lo = nullptr;
+        if (fp32) {
+            if (q.keep_lo) {
+                p.lo = prob->out_lo;
+            } else {
+                p.lo = reinterpret_cast<float *>(base + o_lo) + loff;
+                loff += q.ncell;
+            }
         }
-        if (fp32 && (!accumulate || !keep_lo)) {
-            hipLaunchKernelGGL(k_fill<float>, dim3(grid_blocks(ncell, 256)), dim3(256), 0, stream, p.lo, ncell);
+        p.tinfo = reinterpret_cast<uint32_t *>(base + o_tinfo) + toff;
+        toff += prob->n_simplex;
+        p.items = reinterpret_cast<uint64_t *>(base + o_items);
+        p.item_prob = n > 1 ? reinterpret_cast<uint16_t *>(base + o_iprob) : nullptr;
+        p.extra_cap = extra_cap;
+        p.ovf = reinterpret_cast<Ovf *>(base + o_ovf);
+        p.cs = ctx->cs;
+        p.es = ctx->es;
+        p.slab_group = ctx->tune.slab_group;
+        p.count_pieces = ctx->profiling >= 2;
+    }
+    return SP_OK;
+}
+
+// The kernels of one launch, in stream order.  With timers, each stage is
+// bracketed by HIP events (profiling of direct calls; captured graphs are
+// timed as a whole).
+template <int D, typename T>
+static void enqueue(sp_ctx *ctx, const std::vector<Prepared<T>> &v, const Batch &b, int64_t ntotal, hipStream_t stream,
+                    bool timers)
+{
+    const bool fp32 = sizeof(T) == 4;
+    const bool single = b.nprob == 0;
+    const ProbDev<T> &p0 = v[0].p;
+    auto timer = [&](int stage) { return StageTimer(timers ? ctx : nullptr, stream, &ctx->ev[stage]); };
+    {
+        StageTimer t = timer(ST_FILL);
+        hipLaunchKernelGGL(k_clear_state, dim3(1), dim3(64), 0, stream, ctx->cs, single ? v[0].total : nullptr);
+        for (const Prepared<T> &q : v) {
+            if (!single && q.total) hipLaunchKernelGGL(k_fill<double>, dim3(1), dim3(64), 0, stream, q.total, (size_t)1);
+            if (!q.accumulate)
+                hipLaunchKernelGGL(k_fill<T>, dim3(grid_blocks(q.ncell, 256)), dim3(256), 0, stream, q.p.out, q.ncell);
+            if (fp32 && (!q.accumulate || !q.keep_lo))
+                hipLaunchKernelGGL(k_fill<float>, dim3(grid_blocks(q.ncell, 256)), dim3(256), 0, stream, q.p.lo, q.ncell);
         }
     }
-    if (n > 0) {
-        int nb = (int)((n + 255) / 256);
+    if (ntotal > 0) {
+        const int nb = (int)((ntotal + 255) / 256);
         {
-            StageTimer t(ctx, stream, &ctx->ev[ST_SETUP]);
-            hipLaunchKernelGGL((k_setup<D, T>), dim3(nb), dim3(256), 0, stream, p);
+            StageTimer t = timer(ST_SETUP);
+            hipLaunchKernelGGL((k_setup<D, T>), dim3(nb), dim3(256), 0, stream, p0, b);
         }
         {
-            StageTimer t(ctx, stream, &ctx->ev[ST_BIN]);
+            StageTimer t = timer(ST_BIN);
             hipLaunchKernelGGL(k_scan, dim3(1), dim3(64), 0, stream, ctx->cs);
-            hipLaunchKernelGGL((k_scatter<T>), dim3(nb), dim3(256), 0, stream, p);
+            hipLaunchKernelGGL((k_scatter<T>), dim3(nb), dim3(256), 0, stream, p0, b);
         }
         int occ = 0;
         (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_clip<D, T, MAXV3>, WG, 0);
         if (occ < 1) occ = 1;
-        int cpc = ctx->tune.chunks_per_cu > 0 ? ctx->tune.chunks_per_cu : occ;
-        int blocks = ctx->num_cu * cpc;
+        const int cpc = ctx->tune.chunks_per_cu > 0 ? ctx->tune.chunks_per_cu : occ;
+        const int blocks = ctx->num_cu * cpc;
         ctx->last_clip_blocks = blocks;
         {
-            StageTimer t(ctx, stream, &ctx->ev[ST_CLIP]);
-            hipLaunchKernelGGL((k_clip<D, T, MAXV3>), dim3(blocks), dim3(WG), 0, stream, p, 0);
+            StageTimer t = timer(ST_CLIP);
+            hipLaunchKernelGGL((k_clip<D, T, MAXV3>), dim3(blocks), dim3(WG), 0, stream, p0, b, 0);
         }
         {
-            StageTimer t(ctx, stream, &ctx->ev[ST_RETRY]);
+            StageTimer t = timer(ST_RETRY);
             if (D == 3) {
-                hipLaunchKernelGGL((k_clip<D, T, MAXV3_BIG>), dim3(ctx->num_cu), dim3(WG), 0, stream, p, 1);
+                hipLaunchKernelGGL((k_clip<D, T, MAXV3_BIG>), dim3(ctx->num_cu), dim3(WG), 0, stream, p0, b, 1);
             } else {
-                hipLaunchKernelGGL((k_clip<D, T, MAXV3>), dim3(ctx->num_cu), dim3(WG), 0, stream, p, 1);
+                hipLaunchKernelGGL((k_clip<D, T, MAXV3>), dim3(ctx->num_cu), dim3(WG), 0, stream, p0, b, 1);
             }
         }
     }
-    double to_mass = 1.0;
-    if (!(prob->grid.flags & SP_OUT_MASS)) {
-        for (int d = 0; d < D; ++d) to_mass *= prob->grid.extent[d] / (double)prob->grid.dims[d];
+    {
+        StageTimer t = timer(ST_FINAL);
+        for (const Prepared<T> &q : v) {
+            if (fp32 || q.total)
+                hipLaunchKernelGGL(k_finalize<T>, dim3(grid_blocks(q.ncell, 256 * 8)), dim3(256), 0, stream, q.p.out,
+                                   q.p.lo, q.keep_lo ? 1 : 0, q.ncell, q.to_mass, q.total);
+        }
     }
-    if (fp32 || total) {
-        StageTimer t(ctx, stream, &ctx->ev[ST_FINAL]);
-        hipLaunchKernelGGL(k_finalize<T>, dim3(grid_blocks(ncell, 256 * 8)), dim3(256), 0, stream, p.out,
-                           p.lo, keep_lo ? 1 : 0, ncell, to_mass, total);
+}
+
+template <int D, typename T>
+static sp_status project_impl(sp_ctx *ctx, const sp_problem *prob, hipStream_t stream)
+{
+    HIPCHECK(hipSetDevice(ctx->device));
+    std::vector<Prepared<T>> v;
+    int64_t ntotal = 0;
+    sp_status st = prepare<D, T>(ctx, prob, 1, v, ntotal);
+    if (st != SP_OK) return st;
+    Batch b = {nullptr, nullptr, 0, ntotal};
+    if (ctx->profiling) ctx->prof_calls++;
+    {
+        StageTimer whole(ctx->profiling ? ctx : nullptr, stream, &ctx->ev_call);
+        enqueue<D, T>(ctx, v, b, ntotal, stream, ctx->profiling != 0);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(SP_E_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
@@ -838,7 +987,7 @@ extern "C" sp_status sp_project_tets(sp_ctx *ctx, const sp_problem *prob, sp_pre
     if (st != SP_OK) return st;
     if (!ctx) return fail(SP_E_INVALID_ARG, "ctx is NULL");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    return prec == SP_PREC_FP32C ? project_impl<3, float>(ctx, prob, prec, s) : project_impl<3, double>(ctx, prob, prec, s);
+    return prec == SP_PREC_FP32C ? project_impl<3, float>(ctx, prob, s) : project_impl<3, double>(ctx, prob, s);
 }
 
 extern "C" sp_status sp_project_tris(sp_ctx *ctx, const sp_problem *prob, sp_precision prec, void *stream)
@@ -847,19 +996,100 @@ extern "C" sp_status sp_project_tris(sp_ctx *ctx, const sp_problem *prob, sp_pre
     if (st != SP_OK) return st;
     if (!ctx) return fail(SP_E_INVALID_ARG, "ctx is NULL");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    return prec == SP_PREC_FP32C ? project_impl<2, float>(ctx, prob, prec, s) : project_impl<2, double>(ctx, prob, prec, s);
+    return prec == SP_PREC_FP32C ? project_impl<2, float>(ctx, prob, s) : project_impl<2, double>(ctx, prob, s);
+}
+
+// FNV-1a over the bytes that determine a batched launch.
+static uint64_t fnv(uint64_t h, const void *data, size_t n)
+{
+    const unsigned char *c = static_cast<const unsigned char *>(data);
+    for (size_t i = 0; i < n; ++i) {
+        h ^= c[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+template <typename T>
+static sp_status batch_impl(sp_ctx *ctx, const sp_problem *probs, int n, sp_precision prec, hipStream_t stream)
+{
+    HIPCHECK(hipSetDevice(ctx->device));
+    std::vector<Prepared<T>> v;
+    int64_t ntotal = 0;
+    sp_status st = prepare<3, T>(ctx, probs, n, v, ntotal);
+    if (st != SP_OK) return st;
+    uint64_t key = 1469598103934665603ull;
+    key = fnv(key, &prec, sizeof prec);
+    key = fnv(key, &n, sizeof n);
+    key = fnv(key, probs, sizeof(sp_problem) * (size_t)n);
+    key = fnv(key, &ctx->tune, sizeof ctx->tune);
+    const int pmode = ctx->profiling >= 2 ? 2 : 0;
+    key = fnv(key, &pmode, sizeof pmode);
+    key = fnv(key, &ctx->scratch, sizeof ctx->scratch);
+    GraphEntry *ge = nullptr;
+    for (GraphEntry &g : ctx->graphs)
+        if (g.key == key) ge = &g;
+    if (!ge) {
+        if (ctx->graphs.size() >= 16) drop_graphs(ctx);
+        GraphEntry g;
+        g.key = key;
+        g.exec = nullptr;
+        g.dev = nullptr;
+        // descriptors and simplex offsets, uploaded once for this signature
+        const size_t bytes = sizeof(ProbDev<T>) * (size_t)n + sizeof(int64_t) * (size_t)(n + 1);
+        HIPCHECK(hipMalloc(&g.dev, bytes));
+        std::vector<unsigned char> host(bytes);
+        std::vector<int64_t> offs(n + 1, 0);
+        for (int i = 0; i < n; ++i) {
+            memcpy(host.data() + sizeof(ProbDev<T>) * i, &v[i].p, sizeof(ProbDev<T>));
+            offs[i + 1] = offs[i] + probs[i].n_simplex;
+        }
+        memcpy(host.data() + sizeof(ProbDev<T>) * n, offs.data(), sizeof(int64_t) * (n + 1));
+        HIPCHECK(hipMemcpy(g.dev, host.data(), bytes, hipMemcpyHostToDevice));
+        Batch b;
+        b.probs = g.dev;
+        b.offs = reinterpret_cast<const int64_t *>(static_cast<char *>(g.dev) + sizeof(ProbDev<T>) * n);
+        b.nprob = n;
+        b.ntotal = ntotal;
+        // capture the whole launch sequence once; replays cost one launch
+        hipGraph_t graph = nullptr;
+        HIPCHECK(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+        enqueue<3, T>(ctx, v, b, ntotal, ctx->cap_stream, false);
+        hipError_t e1 = hipStreamEndCapture(ctx->cap_stream, &graph);
+        if (e1 != hipSuccess) {
+            (void)hipFree(g.dev);
+            return fail(SP_E_DEVICE, "graph capture failed: %s", hipGetErrorString(e1));
+        }
+        hipError_t e2 = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e2 != hipSuccess) {
+            (void)hipFree(g.dev);
+            return fail(SP_E_DEVICE, "graph instantiation failed: %s", hipGetErrorString(e2));
+        }
+        ctx->graphs.push_back(g);
+        ge = &ctx->graphs.back();
+    }
+    if (ctx->profiling) ctx->prof_calls++;
+    {
+        StageTimer whole(ctx->profiling ? ctx : nullptr, stream, &ctx->ev_call);
+        HIPCHECK(hipGraphLaunch(ge->exec, stream));
+    }
+    return SP_OK;
 }
 
 extern "C" sp_status sp_project_batch(sp_ctx *ctx, int dim, const sp_problem *probs, int n, sp_precision prec, void *stream)
 {
-    if (!ctx) return fail(SP_E_INVALID_ARG, "ctx is NULL");
     if (dim != 3) return fail(SP_E_UNSUPPORTED, "batched projection supports dim 3 only");
     if (n < 0 || (n > 0 && !probs)) return fail(SP_E_INVALID_ARG, "bad problem array");
+    if (n > 65535) return fail(SP_E_INVALID_ARG, "at most 65535 problems per batch");
     for (int i = 0; i < n; ++i) {
-        sp_status st = sp_project_tets(ctx, &probs[i], prec, stream);
+        sp_status st = check_problem(&probs[i], 3, prec);
         if (st != SP_OK) return st;
     }
-    return SP_OK;
+    if (!ctx) return fail(SP_E_INVALID_ARG, "ctx is NULL");
+    if (n == 0) return SP_OK;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    return prec == SP_PREC_FP32C ? batch_impl<float>(ctx, probs, n, prec, s) : batch_impl<double>(ctx, probs, n, prec, s);
 }
 
 extern "C" sp_status sp_sync_status(sp_ctx *ctx, void *stream)
@@ -931,14 +1161,129 @@ extern "C" sp_status sp_profile_read(sp_ctx *ctx, sp_profile *out)
     return SP_OK;
 }
 
+// Launch parameters the autotuner searches: the slab group (how many
+// x-slabs one work item covers) and the clip blocks per CU (0 = as many as
+// fit).
+static const int kTuneSlab[] = {1, 2, 4, 8, 16};
+static const int kTuneBlocks[] = {0, 4};
+
+// Signature of a tuning sample: what determines the best parameters, not
+// where the buffers live.
+static uint64_t sample_signature(int dim, const sp_problem *sample, int n, sp_precision prec, int num_cu)
+{
+    uint64_t h = 1469598103934665603ull;
+    h = fnv(h, &dim, sizeof dim);
+    h = fnv(h, &prec, sizeof prec);
+    h = fnv(h, &num_cu, sizeof num_cu);
+    for (int i = 0; i < n; ++i) {
+        h = fnv(h, &sample[i].n_vert, sizeof sample[i].n_vert);
+        h = fnv(h, &sample[i].n_simplex, sizeof sample[i].n_simplex);
+        h = fnv(h, &sample[i].grid, sizeof sample[i].grid);
+    }
+    return h;
+}
+
+static bool cache_lookup(const char *path, uint64_t sig, Tuning &t)
+{
+    FILE *f = fopen(path, "r");
+    if (!f) return false;
+    char line[256];
+    bool found = false;
+    while (fgets(line, sizeof line, f)) {
+        unsigned long long k = 0;
+        int g = 0, c = 0;
+        if (sscanf(line, "simproj-tune 1 sig=%llx slab_group=%d blocks_per_cu=%d", &k, &g, &c) == 3 && k == sig &&
+            g > 0 && g <= 4095 && c >= 0) {
+            t.slab_group = g;
+            t.chunks_per_cu = c;
+            found = true;
+        }
+    }
+    fclose(f);
+    return found;
+}
+
 extern "C" sp_status sp_autotune(sp_ctx *ctx, int dim, const sp_problem *sample, int n, sp_precision prec,
                                  const char *cache_path)
 {
+    if (dim != 2 && dim != 3) return fail(SP_E_INVALID_ARG, "dim must be 2 or 3");
+    if (n <= 0 || !sample) return fail(SP_E_INVALID_ARG, "an autotuning sample needs at least one problem");
+    for (int i = 0; i < n; ++i) {
+        sp_status st = check_problem(&sample[i], dim, prec);
+        if (st != SP_OK) return st;
+    }
     if (!ctx) return fail(SP_E_INVALID_ARG, "ctx is NULL");
-    (void)dim;
-    (void)sample;
-    (void)n;
-    (void)prec;
-    (void)cache_path;
-    return fail(SP_E_UNSUPPORTED, "autotuning is not available in this build");
+    HIPCHECK(hipSetDevice(ctx->device));
+    const uint64_t sig = sample_signature(dim, sample, n, prec, ctx->num_cu);
+    Tuning best = ctx->tune;
+    if (cache_path && cache_lookup(cache_path, sig, best)) {
+        ctx->tune = best;
+        return SP_OK;
+    }
+    const int saved_prof = ctx->profiling;
+    ctx->profiling = 0;
+    hipStream_t s = ctx->cap_stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHECK(hipEventCreate(&e0));
+    HIPCHECK(hipEventCreate(&e1));
+    float best_ms = 1e30f;
+    sp_status st = SP_OK;
+    for (int g : kTuneSlab) {
+        for (int c : kTuneBlocks) {
+            ctx->tune.slab_group = g;
+            ctx->tune.chunks_per_cu = c;
+            float ms = 0.f;
+            for (int rep = 0; rep < 3 && st == SP_OK; ++rep) {  // one warm-up, then the best of two
+                (void)hipEventRecord(e0, s);
+                for (int i = 0; i < n && st == SP_OK; ++i)
+                    st = dim == 3 ? (prec == SP_PREC_FP32C ? project_impl<3, float>(ctx, &sample[i], s)
+                                                           : project_impl<3, double>(ctx, &sample[i], s))
+                                  : (prec == SP_PREC_FP32C ? project_impl<2, float>(ctx, &sample[i], s)
+                                                           : project_impl<2, double>(ctx, &sample[i], s));
+                (void)hipEventRecord(e1, s);
+                if (hipEventSynchronize(e1) != hipSuccess) st = fail(SP_E_DEVICE, "autotune run failed");
+                float t = 0.f;
+                (void)hipEventElapsedTime(&t, e0, e1);
+                if (rep == 1 || (rep == 2 && t < ms)) ms = t;
+            }
+            if (st != SP_OK) break;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = ctx->tune;
+            }
+        }
+        if (st != SP_OK) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    ctx->profiling = saved_prof;
+    ctx->tune = best;
+    if (st != SP_OK) return st;
+    if (cache_path) {
+        FILE *f = fopen(cache_path, "a");
+        if (!f) return fail(SP_E_INVALID_ARG, "cannot write the tuning cache %s", cache_path);
+        fprintf(f, "simproj-tune 1 sig=%llx slab_group=%d blocks_per_cu=%d ms=%.4f\n", (unsigned long long)sig,
+                best.slab_group, best.chunks_per_cu, best_ms);
+        fclose(f);
+    }
+    return SP_OK;
+}
+
+extern "C" sp_status sp_tuning_set(sp_ctx *ctx, int slab_group, int blocks_per_cu)
+{
+    if (!ctx) return fail(SP_E_INVALID_ARG, "ctx is NULL");
+    if (slab_group < 1 || slab_group > 4095) return fail(SP_E_INVALID_ARG, "slab_group %d not in 1..4095", slab_group);
+    if (blocks_per_cu < 0 || blocks_per_cu > 64)
+        return fail(SP_E_INVALID_ARG, "blocks_per_cu %d not in 0..64", blocks_per_cu);
+    ctx->tune.slab_group = slab_group;
+    ctx->tune.chunks_per_cu = blocks_per_cu;
+    return SP_OK;
+}
+
+extern "C" sp_status sp_tuning_read(sp_ctx *ctx, int *slab_group, int *blocks_per_cu)
+{
+    if (!ctx) return fail(SP_E_INVALID_ARG, "ctx is NULL");
+    if (slab_group) *slab_group = ctx->tune.slab_group;
+    if (blocks_per_cu) *blocks_per_cu = ctx->tune.chunks_per_cu;
+    return SP_OK;
 }

@@ -80,6 +80,10 @@ _lib.sp_sync_status.restype = ctypes.c_int
 _lib.sp_autotune.argtypes = [_V, ctypes.c_int, ctypes.POINTER(sp_problem), ctypes.c_int, ctypes.c_int,
                              ctypes.c_char_p]
 _lib.sp_autotune.restype = ctypes.c_int
+_lib.sp_tuning_read.argtypes = [_V, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+_lib.sp_tuning_read.restype = ctypes.c_int
+_lib.sp_tuning_set.argtypes = [_V, ctypes.c_int, ctypes.c_int]
+_lib.sp_tuning_set.restype = ctypes.c_int
 _lib.sp_profile_enable.argtypes = [_V, ctypes.c_int]
 _lib.sp_profile_enable.restype = ctypes.c_int
 _lib.sp_profile_read.argtypes = [_V, ctypes.POINTER(sp_profile)]
@@ -135,6 +139,16 @@ def sp_autotune(ctx, dim: int, sample: Sequence[sp_problem], prec: int, cache_pa
     arr = (sp_problem * len(sample))(*sample)
     cp = cache_path.encode() if cache_path else None
     return _lib.sp_autotune(ctx, int(dim), arr, len(sample), int(prec), cp)
+
+
+def sp_tuning_read(ctx):
+    g, c = ctypes.c_int(), ctypes.c_int()
+    st = _lib.sp_tuning_read(ctx, ctypes.byref(g), ctypes.byref(c))
+    return st, g.value, c.value
+
+
+def sp_tuning_set(ctx, slab_group: int, blocks_per_cu: int) -> int:
+    return _lib.sp_tuning_set(ctx, int(slab_group), int(blocks_per_cu))
 
 
 def sp_profile_enable(ctx, on: int) -> int:
@@ -242,6 +256,27 @@ class Context:
         fn = sp_project_tets if dim == 3 else sp_project_tris
         _check(fn(self.handle, p, prec, _stream_ptr(stream)), fn.__name__)
         return out, total
+
+    def project_batch(self, problems, precision: str = "fp32c", stream=None) -> None:
+        """Project several 3D problems (sp_problem records built with
+        make_problem; their tensors must stay alive) in one launch."""
+        prec = SP_PREC_FP32C if precision == "fp32c" else SP_PREC_FP64
+        _check(sp_project_batch(self.handle, 3, list(problems), prec, _stream_ptr(stream)), "sp_project_batch")
+
+    def autotune(self, dim: int, sample, precision: str = "fp32c", cache_path: Optional[str] = None):
+        """Tune the launch parameters on sample problems; returns
+        (slab_group, blocks_per_cu) now in use."""
+        prec = SP_PREC_FP32C if precision == "fp32c" else SP_PREC_FP64
+        _check(sp_autotune(self.handle, dim, list(sample), prec, cache_path), "sp_autotune")
+        return self.tuning()
+
+    def set_tuning(self, slab_group: int, blocks_per_cu: int = 0) -> None:
+        _check(sp_tuning_set(self.handle, slab_group, blocks_per_cu), "sp_tuning_set")
+
+    def tuning(self):
+        st, g, c = sp_tuning_read(self.handle)
+        _check(st, "sp_tuning_read")
+        return g, c
 
     def sync_status(self, stream=None) -> int:
         return sp_sync_status(self.handle, _stream_ptr(stream))

@@ -1,0 +1,210 @@
+"""The batched launch (sp_project_batch), its graph replays, the launch
+parameters (sp_tuning_set) and the autotuner (sp_autotune), through the C ABI.
+
+Each batched result is compared with the oracle at the parity tolerances and
+with one sp_project_tets call per problem; results must not depend on the
+launch parameters."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1509_07720_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1509_07720_amd import simproj  # noqa: E402
+
+TOL = {"fp64": (1e-12, 1e-12), "fp32c": (1e-5, 1e-7)}
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = simproj.Context(0)
+    yield c
+    c.close()
+
+
+def _spans_ok(prob):
+    P = synth.unwrapped_corners(prob["xyz"], prob["simplices"], prob["extent"], prob["periodic"])
+    return bool(np.all(P.max(axis=1) - P.min(axis=1) < 0.45 * np.asarray(prob["extent"])))
+
+
+def small_batch(count=6, seed_base=4000):
+    """The batched workload's recipe at reduced sizes (uneven meshes and grids).
+    At these sizes a few lattices are displaced so far that some tetrahedra
+    span half the box (skipped by both sides); such items are left out."""
+    out = []
+    seed = seed_base
+    while len(out) < count:
+        (p,) = synth.batch_3d(count=1, seed_base=seed, nmin=2e3, nmax=6e4, smin=16, smax=64)
+        if _spans_ok(p):
+            out.append(p)
+        seed += 1
+    return out
+
+
+class Dev:
+    """One problem's device buffers and its sp_problem record."""
+
+    def __init__(self, prob, prec, accumulate=False, keep_lo=False):
+        dt = torch.float32 if prec == "fp32c" else torch.float64
+        d = torch.device("cuda:0")
+        self.prob = prob
+        self.xyz = torch.tensor(np.asarray(prob["xyz"]), dtype=dt, device=d).contiguous()
+        self.simp = torch.tensor(np.asarray(prob["simplices"]), dtype=torch.int32, device=d).contiguous()
+        self.rho = torch.tensor(np.asarray(prob["rho"]), dtype=dt, device=d).contiguous()
+        self.out = torch.zeros(tuple(reversed(prob["dims"])), dtype=dt, device=d)
+        self.lo = torch.zeros_like(self.out, dtype=torch.float32) if keep_lo else None
+        self.total = torch.zeros(1, dtype=torch.float64, device=d)
+        self.rec = simproj.make_problem(self.xyz, self.simp, self.rho, prob["dims"], prob["origin"], prob["extent"],
+                                        prob["periodic"], prob["rho_per_corner"], self.out, self.lo, self.total,
+                                        out_mass=True, accumulate=accumulate, validate=True)
+
+    def grid(self):
+        g = self.out.double()
+        if self.lo is not None:
+            g = g + self.lo.double()
+        return g.cpu().numpy()
+
+
+def _ref(prob, prec):
+    return oracle.project(synth.as_float32(prob) if prec == "fp32c" else prob)
+
+
+def _assert_parity(got, ref, prec, what):
+    err = oracle.cell_error(got, ref)
+    tc, tm = TOL[prec]
+    assert err["e_cell"] <= tc, (what, err)
+    assert err["e_mass"] <= tm, (what, err)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_batch_matches_oracle_and_single_calls(ctx, prec):
+    probs = small_batch()
+    sizes = [p["simplices"].shape[0] for p in probs]
+    print("batch sizes", sizes, [p["dims"][0] for p in probs], flush=True)
+    devs = [Dev(synth.as_float32(p) if prec == "fp32c" else p, prec) for p in probs]
+    ctx.project_batch([d.rec for d in devs], precision=prec)
+    assert ctx.sync_status() == simproj.SP_OK, simproj.sp_last_error()
+    for i, (p, d) in enumerate(zip(probs, devs)):
+        ref = _ref(p, prec)
+        got = d.grid()
+        _assert_parity(got, ref, prec, f"problem {i}")
+        tot = float(d.total.cpu()[0])
+        assert abs(tot - ref["mass"].sum()) <= TOL[prec][1] * abs(ref["mass"].sum()), i
+        single = Dev(synth.as_float32(p) if prec == "fp32c" else p, prec)
+        st = simproj.sp_project_tets(ctx.handle, single.rec, simproj.SP_PREC_FP32C if prec == "fp32c"
+                                     else simproj.SP_PREC_FP64, simproj._stream_ptr(None))
+        assert st == simproj.SP_OK
+        assert ctx.sync_status() == simproj.SP_OK
+        scale = max(np.abs(ref["cov"]).max(), np.abs(got).max())
+        assert np.abs(single.grid() - got).max() <= TOL[prec][0] * scale, i
+
+
+def test_batch_graph_replays_read_live_inputs(ctx):
+    """Replays of the captured launch, with eager work and synchronisations
+    between them: each replay must equal the eager per-problem result for the
+    inputs present at that time (the densities are rescaled in place)."""
+    prec = "fp32c"
+    probs = [synth.as_float32(p) for p in small_batch(count=4, seed_base=4100)]
+    devs = [Dev(p, prec) for p in probs]
+    refs = [_ref(p, prec) for p in probs]
+    recs = [d.rec for d in devs]
+    scratch = torch.empty(1 << 20, device="cuda:0")
+    for rep, factor in enumerate([1.0, 1.0, 2.0, 0.5, 1.0]):
+        for d in devs:
+            d.rho.mul_(factor)
+        scratch.normal_()  # unrelated eager work on the same stream
+        torch.cuda.synchronize()
+        ctx.project_batch(recs, precision=prec)
+        assert ctx.sync_status() == simproj.SP_OK, simproj.sp_last_error()
+        scale_now = float(np.prod([1.0, 1.0, 2.0, 0.5, 1.0][:rep + 1]))
+        for i, (d, ref) in enumerate(zip(devs, refs)):
+            ref_s = dict(ref, mass=ref["mass"] * scale_now, cov=ref["cov"] * scale_now)
+            _assert_parity(d.grid(), ref_s, prec, f"replay {rep} problem {i}")
+            assert abs(float(d.total.cpu()[0]) - ref_s["mass"].sum()) <= 1e-7 * abs(ref_s["mass"].sum())
+
+
+def test_batch_per_problem_flags(ctx):
+    """out_lo kept by the caller, accumulation into an existing grid, and a
+    problem with no simplices, side by side in one batch."""
+    prec = "fp32c"
+    probs = [synth.as_float32(p) for p in small_batch(count=3, seed_base=4200)]
+    a = Dev(probs[0], prec, keep_lo=True)
+    b = Dev(probs[1], prec, accumulate=True)
+    base = 2.0 ** -13  # comparable to the cell masses, so FP32 keeps their digits
+    b.out.fill_(base)
+    empty = dict(probs[2], simplices=np.zeros((0, 4), dtype=np.int32))
+    c = Dev(empty, prec)
+    c.out.fill_(5.0)
+    ctx.project_batch([a.rec, b.rec, c.rec], precision=prec)
+    assert ctx.sync_status() == simproj.SP_OK, simproj.sp_last_error()
+    _assert_parity(a.grid(), _ref(probs[0], prec), prec, "keep_lo")
+    ref_b = _ref(probs[1], prec)
+    _assert_parity(b.grid() - base, ref_b, prec, "accumulate")
+    assert np.all(c.grid() == 0.0)
+    assert float(c.total.cpu()[0]) == 0.0
+
+
+def test_batch_rejects_bad_problem_without_launching(ctx):
+    prec = "fp32c"
+    probs = [synth.as_float32(p) for p in small_batch(count=2, seed_base=4300)]
+    devs = [Dev(p, prec) for p in probs]
+    bad = simproj.make_problem(devs[1].xyz, devs[1].simp, devs[1].rho, [0, 8, 8], out=devs[1].out)
+    st = simproj.sp_project_batch(ctx.handle, 3, [devs[0].rec, bad], simproj.SP_PREC_FP32C,
+                                  simproj._stream_ptr(None))
+    assert st == simproj.SP_E_INVALID_ARG
+    assert "dims[0]" in simproj.sp_last_error()
+    torch.cuda.synchronize()
+    assert float(devs[0].out.abs().sum()) == 0.0  # nothing was enqueued
+    st = simproj.sp_project_batch(ctx.handle, 2, [devs[0].rec], simproj.SP_PREC_FP32C, simproj._stream_ptr(None))
+    assert st == simproj.SP_E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("slab_group, blocks", [(1, 0), (2, 4), (16, 0), (4, 1)])
+def test_results_independent_of_launch_parameters(ctx, slab_group, blocks):
+    prec = "fp32c"
+    prob = synth.as_float32(synth.tet_soup(n_tets=20000, grid=256, seed=3))
+    old = ctx.tuning()
+    try:
+        ctx.set_tuning(slab_group, blocks)
+        d = Dev(prob, prec)
+        st = simproj.sp_project_tets(ctx.handle, d.rec, simproj.SP_PREC_FP32C, simproj._stream_ptr(None))
+        assert st == simproj.SP_OK
+        assert ctx.sync_status() == simproj.SP_OK, simproj.sp_last_error()
+        _assert_parity(d.grid(), _ref(prob, prec), prec, (slab_group, blocks))
+    finally:
+        ctx.set_tuning(*old)
+
+
+def test_tuning_set_rejects_out_of_range(ctx):
+    assert simproj.sp_tuning_set(ctx.handle, 0, 0) == simproj.SP_E_INVALID_ARG
+    assert simproj.sp_tuning_set(ctx.handle, 4, 65) == simproj.SP_E_INVALID_ARG
+
+
+def test_autotune_picks_candidate_and_caches(ctx, tmp_path):
+    prec = "fp32c"
+    prob = synth.as_float32(synth.zeldovich_3d(n=24, grid=48, sigma_cells=1.5, seed=7))
+    d = Dev(prob, prec)
+    cache = str(tmp_path / "tune.txt")
+    old = ctx.tuning()
+    try:
+        g, c = ctx.autotune(3, [d.rec], precision=prec, cache_path=cache)
+        assert g in (1, 2, 4, 8, 16) and c in (0, 4)
+        lines = open(cache).read().splitlines()
+        assert len(lines) == 1 and lines[0].startswith("simproj-tune 1 sig=")
+        ctx.set_tuning(3, 2)
+        assert ctx.autotune(3, [d.rec], precision=prec, cache_path=cache) == (g, c)  # read back, not re-timed
+        assert len(open(cache).read().splitlines()) == 1
+        st = simproj.sp_project_tets(ctx.handle, d.rec, simproj.SP_PREC_FP32C, simproj._stream_ptr(None))
+        assert st == simproj.SP_OK
+        assert ctx.sync_status() == simproj.SP_OK
+        _assert_parity(d.grid(), _ref(prob, prec), prec, "after autotune")
+    finally:
+        ctx.set_tuning(*old)
