@@ -9,6 +9,10 @@ deposits, clip-integrate-deposit of every other simplex, and the hi+lo merge
 with the FP64 total-mass reduction.  Inputs are resident in HBM before the
 timed region.  The same workload is also timed in FP64 mode.
 
+With --batch, the batched workload (64 Zel'dovich meshes of 1e4..2e6 tets
+onto grids of 32^3..256^3) is also timed: one captured graph launch for all
+64 problems against 64 sequential calls, in FP32C and FP64.
+
 Prints one JSON line (see the "metric" field).  --gpus above 1 is refused:
 this build measures one GPU.
 """
@@ -25,6 +29,8 @@ import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+COUNTERS = os.path.join(ROOT, "profiles", "k_clip_soup10M_256_fp32c_counters.md")
+MBENCH = os.path.join(ROOT, "paper_1509_07720_amd", "mbench")
 
 # Algorithmic work per deposited piece, FP32 operations: the cut that
 # separates the piece (about 6 new vertices x 10 flops: a division and four
@@ -53,6 +59,101 @@ def exact_total(prob) -> float:
         r = R[s0:s0 + (1 << 21)] if prob["rho_per_corner"] else R[sub]
         tot += float(np.sum(np.abs(synth.signed_volumes(P)) * r.mean(axis=1)))
     return tot
+
+
+def clip_traffic():
+    """HBM bytes per clip launch from the committed FETCH_SIZE / WRITE_SIZE
+    counter runs, each scaled by what the same counter read for a copy kernel
+    of known size; None when the kernels changed since the counters were
+    taken (or no summary exists)."""
+    from paper_1509_07720_amd import build
+
+    if not os.path.exists(COUNTERS):
+        return None, "no counter summary"
+    txt = open(COUNTERS).read()
+    start = txt.find("```json")
+    if start < 0:
+        return None, "counter summary has no json block"
+    rec = json.loads(txt[start + 7:txt.index("```", start + 7)])
+    if rec["source_sha256"] != build.kernel_source_hash():
+        return None, "kernels changed since the counters were taken"
+    f_scale = rec["copy_bytes"] / (rec["copy_fetch_kib"] * 1024.0)
+    w_scale = rec["copy_bytes"] / (rec["copy_write_kib"] * 1024.0)
+    return rec["fetch_kib"] * 1024.0 * f_scale + rec["write_kib"] * 1024.0 * w_scale, "counters"
+
+
+def atomic_peak():
+    """Measured rate of compensated FP32 atomic adds to random cells of a
+    256^3 grid (the deposit's pattern), from the mbench program."""
+    import subprocess
+
+    if not os.path.exists(MBENCH):
+        return None
+    try:
+        out = subprocess.run([MBENCH, "atomic", "64", "3"], capture_output=True, text=True, timeout=120)
+    except (OSError, subprocess.TimeoutExpired):
+        return None
+    rates = [json.loads(l)["adds_per_s"] for l in out.stdout.splitlines()
+             if l.startswith("{") and "returning+compensated" in l]
+    return max(rates) if rates else None
+
+
+def batch_leg(ctx, steps, warmup):
+    """The batched workload: one graph launch for 64 problems against 64
+    sequential calls; FP32C and FP64."""
+    import torch
+
+    from paper_1509_07720_amd import simproj, synth
+
+    t = time.time()
+    probs = synth.batch_3d()
+    log(f"batch: generated {len(probs)} problems in {time.time() - t:.1f}s")
+    res = {"n_problems": len(probs), "n_simplex": int(sum(p["simplices"].shape[0] for p in probs)),
+           "cells": int(sum(int(np.prod(p["dims"])) for p in probs))}
+    dev = torch.device("cuda:0")
+    for prec in ("fp32c", "fp64"):
+        dt = torch.float32 if prec == "fp32c" else torch.float64
+        code = simproj.SP_PREC_FP32C if prec == "fp32c" else simproj.SP_PREC_FP64
+        keep, recs = [], []
+        for p in probs:
+            xyz = torch.tensor(np.asarray(p["xyz"]), dtype=dt, device=dev)
+            simp = torch.tensor(np.asarray(p["simplices"]), dtype=torch.int32, device=dev)
+            rho = torch.tensor(np.asarray(p["rho"]), dtype=dt, device=dev)
+            out = torch.empty(tuple(reversed(list(p["dims"]))), dtype=dt, device=dev)
+            keep.append((xyz, simp, rho, out))
+            recs.append(simproj.make_problem(xyz, simp, rho, p["dims"], p["origin"], p["extent"], p["periodic"],
+                                             p["rho_per_corner"], out, out_mass=True))
+        stream = simproj._stream_ptr(None)
+
+        def batched():
+            simproj._check(simproj.sp_project_batch(ctx.handle, 3, recs, code, stream), "sp_project_batch")
+
+        def sequential():
+            for r in recs:
+                simproj._check(simproj.sp_project_tets(ctx.handle, r, code, stream), "sp_project_tets")
+
+        t = time.perf_counter()
+        batched()  # first call: capture and instantiation
+        torch.cuda.synchronize()
+        first = time.perf_counter() - t
+        row = {"first_call_ms": first * 1e3}
+        for name, fn in (("batched", batched), ("sequential", sequential)):
+            for _ in range(warmup):
+                fn()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(steps):
+                fn()
+            torch.cuda.synchronize()
+            sec = (time.perf_counter() - t) / steps
+            row[name] = {"ms_per_step": sec * 1e3, "value": res["n_simplex"] / sec}
+        res[prec] = row
+        log(f"batch {prec}: batched {row['batched']['ms_per_step']:.1f} ms, "
+            f"sequential {row['sequential']['ms_per_step']:.1f} ms, first call {first * 1e3:.0f} ms")
+        del keep, recs
+        torch.cuda.empty_cache()
+    res["unit"] = "simplices/s"
+    return res
 
 
 def time_steps(ctx, args_dev, steps, warmup, prec):
@@ -84,10 +185,15 @@ def main() -> int:
     ap.add_argument("--cpu-sample", type=int, default=200_000, help="tets projected by the CPU oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--batch", action="store_true", help="also time the 64-problem batched workload")
+    ap.add_argument("--no-atomic-peak", action="store_true", help="skip the atomic-rate measurement (mbench)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (--gpus must be 1)", file=sys.stderr)
         return 2
+
+    # measured in a child process before this one touches the GPU
+    apeak = None if args.no_atomic_peak else atomic_peak()
 
     import torch
 
@@ -145,6 +251,12 @@ def main() -> int:
         log(f"fp64: {sec64 * 1e3:.3f} ms/step, {n / sec64:.3e} tets/s, mass err {err64:.2e}")
         del xyz64, rho64, out64
 
+    batch = batch_leg(ctx, max(1, min(args.steps, 3)), 1) if args.batch else None
+
+    traffic, traffic_src = clip_traffic()
+    deposits_per_s = pieces / (clip_ms * 1e-3)
+    log(f"traffic: {traffic} ({traffic_src}); atomic peak {apeak}")
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -184,8 +296,12 @@ def main() -> int:
         "stages_ms": stages,
         "fp64": fp64,
         "roofline": {"bound": "alu", "kernel": "k_clip", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
-                     "flops_per_piece": FLOPS_PER_PIECE, "clip_ms": clip_ms},
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
+                     "traffic_source": traffic_src, "flops_per_piece": FLOPS_PER_PIECE, "clip_ms": clip_ms,
+                     "hbm_frac_step": hbm_gbs / PEAK_HBM_GBS,
+                     "atomic": {"deposits_per_s": deposits_per_s, "measured_peak_per_s": apeak,
+                                "frac": deposits_per_s / apeak if apeak else None}},
+        "batch": batch,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -100,12 +100,13 @@ struct DepF32 {
     {
         if (ix == suppress_ix && (iy < suppress_iy || (iy == suppress_iy && iz < suppress_iz))) return;
         ++count;
+        // periodic anchors are reduced to [0, dims) and spans are at most
+        // dims, so one conditional subtraction wraps a periodic index
         int c[3] = {anchor[0] + ix, anchor[1] + iy, anchor[2] + iz};
         for (int d = 0; d < 3; ++d) {
             if (periodic[d]) {
-                c[d] %= dims[d];
-                if (c[d] < 0) c[d] += dims[d];
-            } else if (c[d] < 0 || c[d] >= dims[d]) {
+                c[d] = c[d] >= dims[d] ? c[d] - dims[d] : c[d];
+            } else if ((unsigned)c[d] >= (unsigned)dims[d]) {
                 return;
             }
         }
@@ -133,12 +134,13 @@ struct DepF64 {
     {
         if (ix == suppress_ix && (iy < suppress_iy || (iy == suppress_iy && iz < suppress_iz))) return;
         ++count;
+        // periodic anchors are reduced to [0, dims) and spans are at most
+        // dims, so one conditional subtraction wraps a periodic index
         int c[3] = {anchor[0] + ix, anchor[1] + iy, anchor[2] + iz};
         for (int d = 0; d < 3; ++d) {
             if (periodic[d]) {
-                c[d] %= dims[d];
-                if (c[d] < 0) c[d] += dims[d];
-            } else if (c[d] < 0 || c[d] >= dims[d]) {
+                c[d] = c[d] >= dims[d] ? c[d] - dims[d] : c[d];
+            } else if ((unsigned)c[d] >= (unsigned)dims[d]) {
                 return;
             }
         }
@@ -184,35 +186,31 @@ struct ProbDev {
     int count_pieces;
 };
 
-// Several problems in one launch: their descriptors in device memory and
-// the running totals of their simplex counts (offs[nprob] = all simplices).
-// nprob == 0 means a single problem passed by value.
+// Several problems in one launch: their descriptors in device memory and,
+// for the per-simplex kernels, the first 256-thread block of each problem
+// (the blocks of a problem are contiguous, so the problem is uniform per
+// block; boffs[nprob] = all blocks).  nprob == 0 means a single problem
+// passed by value.
 struct Batch {
     const void *probs;
-    const int64_t *offs;
+    const int32_t *boffs;
     int nprob;
-    int64_t ntotal;
 };
 
-// Problem and local simplex index of a flat simplex index.
+// Problem of this block and the index of its first simplex.
 template <typename T>
-__device__ inline void locate(const ProbDev<T> &p0, const Batch &b, int64_t g, ProbDev<T> &p, int64_t &s, int &pi)
+__device__ inline void block_problem(const Batch &b, ProbDev<T> &p, int64_t &s0, int &pi)
 {
-    if (b.nprob == 0) {
-        p = p0;
-        s = g;
-        pi = 0;
-        return;
-    }
+    const int blk = (int)blockIdx.x;
     int lo = 0, hi = b.nprob - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (b.offs[mid] <= g) lo = mid;
+        if (b.boffs[mid] <= blk) lo = mid;
         else hi = mid - 1;
     }
     pi = lo;
     p = static_cast<const ProbDev<T> *>(b.probs)[lo];
-    s = g - b.offs[lo];
+    s0 = (int64_t)(blk - b.boffs[lo]) * blockDim.x;
 }
 
 template <int D>
@@ -228,6 +226,12 @@ __device__ inline int setup_any(const ProbDev<double> &p, int64_t s, bool valida
 
 constexpr SweepOrder kIdentity = {{0, 1, 2}};
 
+__device__ inline int wrap_index(int k, int n)
+{
+    k %= n;
+    return k < 0 ? k + n : k;
+}
+
 // Deposit for a simplex swept in order o (L already relabelled by o).
 template <typename T>
 __device__ inline typename DepFor<T>::type make_dep(const ProbDev<T> &p, const Local<T> &L, const SweepOrder &o);
@@ -239,9 +243,9 @@ __device__ inline DepF32 make_dep<float>(const ProbDev<float> &p, const Local<fl
     d.lo = p.lo;
     const size_t s1 = (size_t)p.g.dims[0], s2 = (size_t)p.g.dims[0] * (size_t)p.g.dims[1];
     for (int k = 0; k < 3; ++k) {
-        d.anchor[k] = L.anchor[k];
         d.dims[k] = sel3(p.g.dims[0], p.g.dims[1], p.g.dims[2], o.ax[k]);
         d.periodic[k] = sel3(p.g.periodic[0], p.g.periodic[1], p.g.periodic[2], o.ax[k]);
+        d.anchor[k] = d.periodic[k] ? wrap_index(L.anchor[k], d.dims[k]) : L.anchor[k];
         d.stride[k] = sel3((size_t)1, s1, s2, o.ax[k]);
     }
     d.scale = (float)p.g.out_scale;
@@ -258,9 +262,9 @@ __device__ inline DepF64 make_dep<double>(const ProbDev<double> &p, const Local<
     d.out = p.out;
     const size_t s1 = (size_t)p.g.dims[0], s2 = (size_t)p.g.dims[0] * (size_t)p.g.dims[1];
     for (int k = 0; k < 3; ++k) {
-        d.anchor[k] = L.anchor[k];
         d.dims[k] = sel3(p.g.dims[0], p.g.dims[1], p.g.dims[2], o.ax[k]);
         d.periodic[k] = sel3(p.g.periodic[0], p.g.periodic[1], p.g.periodic[2], o.ax[k]);
+        d.anchor[k] = d.periodic[k] ? wrap_index(L.anchor[k], d.dims[k]) : L.anchor[k];
         d.stride[k] = sel3((size_t)1, s1, s2, o.ax[k]);
     }
     d.scale = p.g.out_scale;
@@ -318,19 +322,21 @@ __global__ void k_clear_state(CallState *cs, double *total)
     if (threadIdx.x == 0 && total) *total = 0.0;
 }
 
-template <int D, typename T>
+template <int D, typename T, bool BATCH>
 __global__ __launch_bounds__(256) void k_setup(ProbDev<T> p0, Batch b)
 {
     __shared__ unsigned s_hist[NCLS];
     if (threadIdx.x < NCLS) s_hist[threadIdx.x] = 0u;
     __syncthreads();
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t ntotal = b.nprob ? b.ntotal : p0.n;
-    if (g < ntotal) {
-        ProbDev<T> p;
-        int64_t s;
+    ProbDev<T> p = p0;
+    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if constexpr (BATCH) {
+        int64_t s0;
         int pi;
-        locate(p0, b, g, p, s, pi);
+        block_problem(b, p, s0, pi);
+        s = s0 + threadIdx.x;
+    }
+    if (s < p.n) {
         Local<T> L;
         int st = setup_any<D>(p, s, p.validate != 0, L);
         uint32_t info = 0u;
@@ -386,23 +392,23 @@ __global__ void k_scan(CallState *cs)
     }
 }
 
-template <typename T>
+template <typename T, bool BATCH>
 __global__ __launch_bounds__(256) void k_scatter(ProbDev<T> p0, Batch b)
 {
     __shared__ unsigned s_cnt[NCLS];
     __shared__ unsigned s_base[NCLS];
     if (threadIdx.x < NCLS) s_cnt[threadIdx.x] = 0u;
     __syncthreads();
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t ntotal = b.nprob ? b.ntotal : p0.n;
-    ProbDev<T> p;
-    int64_t s = 0;
+    ProbDev<T> p = p0;
+    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int pi = 0;
-    uint32_t info = 0u;
-    if (g < ntotal) {
-        locate(p0, b, g, p, s, pi);
-        info = p.tinfo[s];
+    if constexpr (BATCH) {
+        int64_t s0;
+        block_problem(b, p, s0, pi);
+        s = s0 + threadIdx.x;
     }
+    uint32_t info = 0u;
+    if (s < p.n) info = p.tinfo[s];
     int cls = (int)(info >> 28), nit = (int)((info >> 16) & 0xfffu), sx = (int)(info & 0xffffu);
     unsigned local = 0;
     if (info) local = atomicAdd(&s_cnt[cls], (unsigned)nit);
@@ -418,35 +424,31 @@ __global__ __launch_bounds__(256) void k_scatter(ProbDev<T> p0, Batch b)
             int sc = sx - sb < per ? sx - sb : per;
             if (sc <= 0) sc = 0;
             p0.items[pos + k] = (uint64_t)(uint32_t)s | ((uint64_t)sb << 32) | ((uint64_t)sc << 48);
-            if (b.nprob) p0.item_prob[pos + k] = (uint16_t)pi;
+            if (BATCH) p0.item_prob[pos + k] = (uint16_t)pi;
         }
     }
 }
 
 // The clip kernel.  Persistent one-wave blocks; each wave takes 64 items at
-// a time from the class-ordered list (most expensive first) into an LDS
-// queue, and every lane pulls its next item from that queue the moment it
-// finishes the previous one, so lanes do not wait for the slowest item of a
-// chunk.  Per loop iteration a busy lane performs one sweep step (a column
-// build if due, then one piece).
+// a time from the class-ordered list (most expensive first), and every lane
+// takes its next item the moment it finishes the previous one, so lanes do
+// not wait for the slowest item of a chunk.  The block is a single wave, so
+// the queue state is wave-uniform (ballots, no LDS and no barriers) and the
+// only LDS is each lane's own polytope.  Per loop iteration a busy lane
+// performs one sweep step (a column build if due, then one piece).
 template <int D, typename T, int MAXV>
 __global__ __launch_bounds__(WG) void k_clip(ProbDev<T> p0, Batch b, int overflow_pass)
 {
+    static_assert(WG == 64, "the queue logic assumes one wave per block");
     const ProbDev<T> &p = p0;  // fields shared by every problem of the launch
     constexpr int SLOTS = D == 3 ? MAXV : 2 * MAXP2;
     __shared__ V4<T> s_p[SLOTS][WG];
     __shared__ uint32_t s_nb[D == 3 ? MAXV : 1][WG];
-    __shared__ unsigned s_base, s_qn, s_qh;
-    __shared__ int s_done;
     const int lane = threadIdx.x;
     const unsigned total = overflow_pass ? min(p.cs->ovf_count, (unsigned)OVF_CAP) : p.cs->total;
     unsigned *head = overflow_pass ? &p.cs->ovf_head : &p.cs->head;
-    if (lane == 0) {
-        s_qn = 0u;
-        s_qh = 0u;
-        s_done = 0;
-        s_base = 0u;
-    }
+    unsigned q_base = 0u, q_n = 0u, q_h = 0u;  // current chunk [q_base, q_base + q_n), next unclaimed q_h
+    bool q_done = false;
     Poly3<T, MAXV, WG> P3;
     P3.p = &s_p[0][lane];
     P3.nb = &s_nb[0][lane];
@@ -462,24 +464,26 @@ __global__ __launch_bounds__(WG) void k_clip(ProbDev<T> p0, Batch b, int overflo
     int64_t sid = 0;
     int sb = 0, sc = 0, pid = 0;
     for (;;) {
-        const int any_idle = __syncthreads_or(!busy);
-        if (any_idle && s_qh >= s_qn && !s_done) {
-            if (lane == 0) s_base = atomicAdd(head, (unsigned)WG);
-            __syncthreads();
-            if (lane == 0) {
-                if (s_base >= total) {
-                    s_done = 1;
-                } else {
-                    s_qn = min((unsigned)WG, total - s_base);
-                    s_qh = 0u;
-                }
+        const uint64_t idle = __ballot(!busy);
+        if (idle != 0ull && q_h >= q_n && !q_done) {
+            unsigned base = 0u;
+            if (lane == 0) base = atomicAdd(head, (unsigned)WG);
+            base = __builtin_amdgcn_readfirstlane(base);
+            if (base >= total) {
+                q_done = true;
+            } else {
+                q_base = base;
+                q_n = min((unsigned)WG, total - base);
+                q_h = 0u;
             }
-            __syncthreads();
         }
-        if (!busy && s_qh < s_qn) {
-            const unsigned k = atomicAdd(&s_qh, 1u);
-            if (k < s_qn) {
-                const unsigned it = s_base + k;
+        if (!busy && q_h < q_n) {
+            // idle lanes take consecutive entries in lane order
+            const unsigned rank = __builtin_amdgcn_mbcnt_hi((unsigned)(idle >> 32),
+                                                            __builtin_amdgcn_mbcnt_lo((unsigned)idle, 0u));
+            const unsigned k = q_h + rank;
+            if (k < q_n) {
+                const unsigned it = q_base + k;
                 int ry = 0, rz = 0;
                 if (overflow_pass) {
                     Ovf o = p.ovf[it];
@@ -512,9 +516,9 @@ __global__ __launch_bounds__(WG) void k_clip(ProbDev<T> p0, Batch b, int overflo
                 }
             }
         }
-        const int any_busy = __syncthreads_or(busy);
-        if (!any_busy) {
-            if (s_done) break;
+        if (q_h < q_n) q_h = min(q_n, q_h + (unsigned)__popcll(idle));
+        if (__ballot(busy) == 0ull) {
+            if (q_done) break;
             continue;
         }
         if (!busy) continue;
@@ -904,7 +908,7 @@ static sp_status prepare(sp_ctx *ctx, const sp_problem *probs, int n, std::vecto
 // bracketed by HIP events (profiling of direct calls; captured graphs are
 // timed as a whole).
 template <int D, typename T>
-static void enqueue(sp_ctx *ctx, const std::vector<Prepared<T>> &v, const Batch &b, int64_t ntotal, hipStream_t stream,
+static void enqueue(sp_ctx *ctx, const std::vector<Prepared<T>> &v, const Batch &b, int64_t nblocks, hipStream_t stream,
                     bool timers)
 {
     const bool fp32 = sizeof(T) == 4;
@@ -922,16 +926,18 @@ static void enqueue(sp_ctx *ctx, const std::vector<Prepared<T>> &v, const Batch 
                 hipLaunchKernelGGL(k_fill<float>, dim3(grid_blocks(q.ncell, 256)), dim3(256), 0, stream, q.p.lo, q.ncell);
         }
     }
-    if (ntotal > 0) {
-        const int nb = (int)((ntotal + 255) / 256);
+    if (nblocks > 0) {
+        const int nb = (int)nblocks;
         {
             StageTimer t = timer(ST_SETUP);
-            hipLaunchKernelGGL((k_setup<D, T>), dim3(nb), dim3(256), 0, stream, p0, b);
+            if (single) hipLaunchKernelGGL((k_setup<D, T, false>), dim3(nb), dim3(256), 0, stream, p0, b);
+            else hipLaunchKernelGGL((k_setup<D, T, true>), dim3(nb), dim3(256), 0, stream, p0, b);
         }
         {
             StageTimer t = timer(ST_BIN);
             hipLaunchKernelGGL(k_scan, dim3(1), dim3(64), 0, stream, ctx->cs);
-            hipLaunchKernelGGL((k_scatter<T>), dim3(nb), dim3(256), 0, stream, p0, b);
+            if (single) hipLaunchKernelGGL((k_scatter<T, false>), dim3(nb), dim3(256), 0, stream, p0, b);
+            else hipLaunchKernelGGL((k_scatter<T, true>), dim3(nb), dim3(256), 0, stream, p0, b);
         }
         int occ = 0;
         (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_clip<D, T, MAXV3>, WG, 0);
@@ -970,11 +976,11 @@ static sp_status project_impl(sp_ctx *ctx, const sp_problem *prob, hipStream_t s
     int64_t ntotal = 0;
     sp_status st = prepare<D, T>(ctx, prob, 1, v, ntotal);
     if (st != SP_OK) return st;
-    Batch b = {nullptr, nullptr, 0, ntotal};
+    Batch b = {nullptr, nullptr, 0};
     if (ctx->profiling) ctx->prof_calls++;
     {
         StageTimer whole(ctx->profiling ? ctx : nullptr, stream, &ctx->ev_call);
-        enqueue<D, T>(ctx, v, b, ntotal, stream, ctx->profiling != 0);
+        enqueue<D, T>(ctx, v, b, (ntotal + 255) / 256, stream, ctx->profiling != 0);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(SP_E_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
@@ -1035,26 +1041,25 @@ static sp_status batch_impl(sp_ctx *ctx, const sp_problem *probs, int n, sp_prec
         g.key = key;
         g.exec = nullptr;
         g.dev = nullptr;
-        // descriptors and simplex offsets, uploaded once for this signature
-        const size_t bytes = sizeof(ProbDev<T>) * (size_t)n + sizeof(int64_t) * (size_t)(n + 1);
+        // descriptors and first set-up blocks, uploaded once for this signature
+        const size_t bytes = sizeof(ProbDev<T>) * (size_t)n + sizeof(int32_t) * (size_t)(n + 1);
         HIPCHECK(hipMalloc(&g.dev, bytes));
         std::vector<unsigned char> host(bytes);
-        std::vector<int64_t> offs(n + 1, 0);
+        std::vector<int32_t> boffs(n + 1, 0);
         for (int i = 0; i < n; ++i) {
             memcpy(host.data() + sizeof(ProbDev<T>) * i, &v[i].p, sizeof(ProbDev<T>));
-            offs[i + 1] = offs[i] + probs[i].n_simplex;
+            boffs[i + 1] = boffs[i] + (int32_t)((probs[i].n_simplex + 255) / 256);
         }
-        memcpy(host.data() + sizeof(ProbDev<T>) * n, offs.data(), sizeof(int64_t) * (n + 1));
+        memcpy(host.data() + sizeof(ProbDev<T>) * n, boffs.data(), sizeof(int32_t) * (n + 1));
         HIPCHECK(hipMemcpy(g.dev, host.data(), bytes, hipMemcpyHostToDevice));
         Batch b;
         b.probs = g.dev;
-        b.offs = reinterpret_cast<const int64_t *>(static_cast<char *>(g.dev) + sizeof(ProbDev<T>) * n);
+        b.boffs = reinterpret_cast<const int32_t *>(static_cast<char *>(g.dev) + sizeof(ProbDev<T>) * n);
         b.nprob = n;
-        b.ntotal = ntotal;
         // capture the whole launch sequence once; replays cost one launch
         hipGraph_t graph = nullptr;
         HIPCHECK(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
-        enqueue<3, T>(ctx, v, b, ntotal, ctx->cap_stream, false);
+        enqueue<3, T>(ctx, v, b, boffs[n], ctx->cap_stream, false);
         hipError_t e1 = hipStreamEndCapture(ctx->cap_stream, &graph);
         if (e1 != hipSuccess) {
             (void)hipFree(g.dev);
