@@ -139,6 +139,29 @@ sp_status sp_project_tris(sp_ctx *ctx, const sp_problem *prob, sp_precision prec
  * split for batches (ms_call only). */
 sp_status sp_project_batch(sp_ctx *ctx, int dim, const sp_problem *probs, int n, sp_precision prec, void *stream);
 
+/* Per-vertex density of a simplicial mesh from the simplex masses: for each
+ * vertex j, rho_j = (sum of M_i) / (sum of |V_i|) over the simplices i
+ * incident to j, |V_i| the unsigned volume (area in 2D) of simplex i in box
+ * units after minimum-image unwrapping on the periodic axes (Section 4,
+ * "Calculation of the acceleration": the estimate that turns simplex masses
+ * into the vertex densities the projection interpolates).
+ *   xyz        device [n_vert][dim], double (SP_PREC_FP64) or float (SP_PREC_FP32C)
+ *   simplices  device [n_simplex][dim+1] int32 vertex indices
+ *   mass       device [n_simplex] masses, same type as xyz; or NULL, then every
+ *              simplex has mass `mass_uniform`
+ *   box        host; only extent[] and the SP_PERIODIC_* flags are used (other
+ *              flags: SP_E_INVALID_ARG)
+ *   rho_out    device [n_vert], same type as xyz; vertices without a simplex of
+ *              non-zero volume get 0
+ * Sums and the division are in FP64 in both precisions (the FP32C result is
+ * the correctly rounded FP64 value up to summation order).  Simplices with an
+ * index out of range or a non-finite coordinate or mass are skipped and
+ * reported by sp_sync_status.  Uses the context's scratch (16 bytes per
+ * vertex); asynchronous on `stream`. */
+sp_status sp_vertex_density(sp_ctx *ctx, int dim, const void *xyz, int64_t n_vert, const int32_t *simplices,
+                            int64_t n_simplex, const void *mass, double mass_uniform, const sp_grid *box,
+                            void *rho_out, sp_precision prec, void *stream);
+
 /* Wait for `stream`, then report the first device-side error recorded since
  * the previous call (SP_VALIDATE checks, capacity failures) and clear it. */
 sp_status sp_sync_status(sp_ctx *ctx, void *stream);

@@ -560,6 +560,69 @@ __global__ __launch_bounds__(WG) void k_clip(ProbDev<T> p0, Batch b, int overflo
     }
 }
 
+// Per-vertex density estimate (Section 4, "Calculation of the acceleration"):
+// rho_j = (sum of the masses of the simplices incident to j) / (sum of their
+// unsigned volumes).  One thread per simplex adds its mass and volume to its
+// D+1 vertices (FP64 atomics, both precisions); a second pass divides.
+template <int D, typename T>
+__global__ __launch_bounds__(256) void k_vd_accum(const T *xyz, int64_t n_vert, const int32_t *simp, int64_t n,
+                                                  const T *mass, double m0, double3 ext, int3 per, double *acc,
+                                                  ErrState *es)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    int32_t vi[D + 1];
+    double x[D + 1][3];
+    for (int a = 0; a <= D; ++a) {
+        vi[a] = simp[s * (D + 1) + a];
+        if (vi[a] < 0 || vi[a] >= n_vert) {
+            record_error(es, SP_E_OUT_OF_RANGE);
+            atomicAdd(&es->n_bad_index, 1);
+            return;
+        }
+        for (int d = 0; d < D; ++d) x[a][d] = (double)xyz[(int64_t)vi[a] * D + d];
+    }
+    const double m = mass ? (double)mass[s] : m0;
+    bool finite = isfinite(m);
+    const double L[3] = {ext.x, ext.y, ext.z};
+    const int P[3] = {per.x, per.y, per.z};
+    double e[D][3];
+    for (int a = 1; a <= D; ++a) {
+        for (int d = 0; d < D; ++d) {
+            double dx = x[a][d] - x[0][d];
+            if (P[d]) dx -= L[d] * rint(dx / L[d]);  // minimum image
+            e[a - 1][d] = dx;
+            finite = finite && isfinite(dx);
+        }
+    }
+    if (!finite) {
+        record_error(es, SP_E_NONFINITE);
+        atomicAdd(&es->n_nonfinite, 1);
+        return;
+    }
+    double vol;
+    if (D == 3) {
+        vol = fabs(e[0][0] * (e[1][1] * e[2][2] - e[1][2] * e[2][1]) - e[0][1] * (e[1][0] * e[2][2] - e[1][2] * e[2][0]) +
+                   e[0][2] * (e[1][0] * e[2][1] - e[1][1] * e[2][0])) /
+              6.0;
+    } else {
+        vol = fabs(e[0][0] * e[1][1] - e[0][1] * e[1][0]) / 2.0;
+    }
+    for (int a = 0; a <= D; ++a) {
+        unsafeAtomicAdd(acc + 2 * (int64_t)vi[a], m);
+        unsafeAtomicAdd(acc + 2 * (int64_t)vi[a] + 1, vol);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_vd_finish(const double *acc, int64_t n_vert, T *rho)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n_vert) return;
+    const double num = acc[2 * j], den = acc[2 * j + 1];
+    rho[j] = den > 0.0 ? (T)(num / den) : T(0);
+}
+
 // hi + lo -> out (unless the caller keeps lo), FP64 total of the grid in mass
 // units.
 template <typename T>
@@ -1095,6 +1158,64 @@ extern "C" sp_status sp_project_batch(sp_ctx *ctx, int dim, const sp_problem *pr
     if (n == 0) return SP_OK;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     return prec == SP_PREC_FP32C ? batch_impl<float>(ctx, probs, n, prec, s) : batch_impl<double>(ctx, probs, n, prec, s);
+}
+
+template <int D, typename T>
+static sp_status vertex_density_impl(sp_ctx *ctx, const void *xyz, int64_t n_vert, const int32_t *simp, int64_t n,
+                                     const void *mass, double m0, const sp_grid *box, void *rho, hipStream_t stream)
+{
+    HIPCHECK(hipSetDevice(ctx->device));
+    if (n_vert == 0) return SP_OK;
+    sp_status st = ensure_scratch(ctx, sizeof(double) * 2 * (size_t)n_vert);
+    if (st != SP_OK) return st;
+    double *acc = reinterpret_cast<double *>(ctx->scratch);
+    const size_t nacc = 2 * (size_t)n_vert;
+    hipLaunchKernelGGL(k_fill<double>, dim3(grid_blocks(nacc, 256)), dim3(256), 0, stream, acc, nacc);
+    if (n > 0) {
+        const double3 ext = make_double3(box->extent[0], box->extent[1], box->extent[2]);
+        const int3 per = make_int3((box->flags & SP_PERIODIC_X) ? 1 : 0, (box->flags & SP_PERIODIC_Y) ? 1 : 0,
+                                   (box->flags & SP_PERIODIC_Z) ? 1 : 0);
+        hipLaunchKernelGGL((k_vd_accum<D, T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream,
+                           reinterpret_cast<const T *>(xyz), n_vert, simp, n, reinterpret_cast<const T *>(mass), m0,
+                           ext, per, acc, ctx->es);
+    }
+    hipLaunchKernelGGL(k_vd_finish<T>, dim3((unsigned)((n_vert + 255) / 256)), dim3(256), 0, stream, acc, n_vert,
+                       reinterpret_cast<T *>(rho));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(SP_E_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+    return SP_OK;
+}
+
+extern "C" sp_status sp_vertex_density(sp_ctx *ctx, int dim, const void *xyz, int64_t n_vert, const int32_t *simplices,
+                                       int64_t n_simplex, const void *mass, double mass_uniform, const sp_grid *box,
+                                       void *rho_out, sp_precision prec, void *stream)
+{
+    if (dim != 2 && dim != 3) return fail(SP_E_INVALID_ARG, "dim must be 2 or 3");
+    if (prec != SP_PREC_FP64 && prec != SP_PREC_FP32C) return fail(SP_E_INVALID_ARG, "unknown precision %d", (int)prec);
+    if (n_vert < 0 || n_vert >= ((int64_t)1 << 31)) return fail(SP_E_INVALID_ARG, "n_vert %lld out of range", (long long)n_vert);
+    if (n_simplex < 0 || n_simplex >= ((int64_t)1 << 31))
+        return fail(SP_E_INVALID_ARG, "n_simplex %lld out of range", (long long)n_simplex);
+    if (!box) return fail(SP_E_INVALID_ARG, "box is NULL");
+    if (box->flags & ~(uint32_t)(SP_PERIODIC_X | SP_PERIODIC_Y | SP_PERIODIC_Z))
+        return fail(SP_E_INVALID_ARG, "only the SP_PERIODIC_* flags apply to sp_vertex_density");
+    for (int d = 0; d < dim; ++d) {
+        if (((box->flags >> d) & 1u) && !(box->extent[d] > 0.0 && box->extent[d] < 1e300))
+            return fail(SP_E_INVALID_ARG, "extent[%d] must be positive and finite on a periodic axis", d);
+    }
+    if (n_vert > 0 && (!xyz || !rho_out)) return fail(SP_E_INVALID_ARG, "xyz and rho_out must not be NULL");
+    if (n_simplex > 0 && !simplices) return fail(SP_E_INVALID_ARG, "simplices must not be NULL");
+    if (n_simplex > 0 && n_vert == 0) return fail(SP_E_INVALID_ARG, "simplices given without vertices");
+    if (!mass && !(mass_uniform == mass_uniform && fabs(mass_uniform) < 1e300))
+        return fail(SP_E_INVALID_ARG, "mass_uniform must be finite");
+    if (!ctx) return fail(SP_E_INVALID_ARG, "ctx is NULL");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (dim == 3)
+        return prec == SP_PREC_FP32C
+                   ? vertex_density_impl<3, float>(ctx, xyz, n_vert, simplices, n_simplex, mass, mass_uniform, box, rho_out, s)
+                   : vertex_density_impl<3, double>(ctx, xyz, n_vert, simplices, n_simplex, mass, mass_uniform, box, rho_out, s);
+    return prec == SP_PREC_FP32C
+               ? vertex_density_impl<2, float>(ctx, xyz, n_vert, simplices, n_simplex, mass, mass_uniform, box, rho_out, s)
+               : vertex_density_impl<2, double>(ctx, xyz, n_vert, simplices, n_simplex, mass, mass_uniform, box, rho_out, s);
 }
 
 extern "C" sp_status sp_sync_status(sp_ctx *ctx, void *stream)

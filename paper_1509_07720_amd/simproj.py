@@ -84,6 +84,9 @@ _lib.sp_tuning_read.argtypes = [_V, ctypes.POINTER(ctypes.c_int), ctypes.POINTER
 _lib.sp_tuning_read.restype = ctypes.c_int
 _lib.sp_tuning_set.argtypes = [_V, ctypes.c_int, ctypes.c_int]
 _lib.sp_tuning_set.restype = ctypes.c_int
+_lib.sp_vertex_density.argtypes = [_V, ctypes.c_int, _V, ctypes.c_int64, _V, ctypes.c_int64, _V, ctypes.c_double,
+                                   ctypes.POINTER(sp_grid), _V, ctypes.c_int, _V]
+_lib.sp_vertex_density.restype = ctypes.c_int
 _lib.sp_profile_enable.argtypes = [_V, ctypes.c_int]
 _lib.sp_profile_enable.restype = ctypes.c_int
 _lib.sp_profile_read.argtypes = [_V, ctypes.POINTER(sp_profile)]
@@ -139,6 +142,12 @@ def sp_autotune(ctx, dim: int, sample: Sequence[sp_problem], prec: int, cache_pa
     arr = (sp_problem * len(sample))(*sample)
     cp = cache_path.encode() if cache_path else None
     return _lib.sp_autotune(ctx, int(dim), arr, len(sample), int(prec), cp)
+
+
+def sp_vertex_density(ctx, dim: int, xyz, n_vert: int, simplices, n_simplex: int, mass, mass_uniform: float,
+                      box: sp_grid, rho_out, prec: int, stream=None) -> int:
+    return _lib.sp_vertex_density(ctx, int(dim), xyz, int(n_vert), simplices, int(n_simplex), mass,
+                                  float(mass_uniform), ctypes.byref(box), rho_out, int(prec), stream)
 
 
 def sp_tuning_read(ctx):
@@ -256,6 +265,35 @@ class Context:
         fn = sp_project_tets if dim == 3 else sp_project_tris
         _check(fn(self.handle, p, prec, _stream_ptr(stream)), fn.__name__)
         return out, total
+
+    def vertex_density(self, xyz, simplices, mass=None, mass_uniform: float = 1.0, extent=(1.0, 1.0, 1.0),
+                       periodic=(True, True, True), precision: str = "fp32c", out=None, stream=None):
+        """Per-vertex density sum(M_i) / sum(|V_i|) over incident simplices
+        (sp_vertex_density); returns a device tensor [n_vert]."""
+        import torch
+
+        dim = int(xyz.shape[1])
+        prec = SP_PREC_FP32C if precision == "fp32c" else SP_PREC_FP64
+        dt = torch.float32 if prec == SP_PREC_FP32C else torch.float64
+        if xyz.dtype != dt or (mass is not None and mass.dtype != dt):
+            raise TypeError(f"xyz and mass must be {dt} for precision {precision}")
+        if simplices.dtype != torch.int32:
+            raise TypeError("simplices must be int32")
+        for t in (xyz, simplices) + ((mass,) if mass is not None else ()):
+            if not t.is_cuda or not t.is_contiguous():
+                raise ValueError("inputs must be contiguous device tensors")
+        if out is None:
+            out = torch.empty(int(xyz.shape[0]), dtype=dt, device=xyz.device)
+        box = sp_grid()
+        for d in range(3):
+            box.extent[d] = float(extent[d]) if d < len(extent) else 1.0
+        box.flags = sum(1 << d for d in range(min(3, len(periodic))) if periodic[d])
+        st = sp_vertex_density(self.handle, dim, xyz.data_ptr() if xyz.numel() else None, int(xyz.shape[0]),
+                               simplices.data_ptr() if simplices.numel() else None, int(simplices.shape[0]),
+                               mass.data_ptr() if mass is not None else None, mass_uniform, box,
+                               out.data_ptr() if out.numel() else None, prec, _stream_ptr(stream))
+        _check(st, "sp_vertex_density")
+        return out
 
     def project_batch(self, problems, precision: str = "fp32c", stream=None) -> None:
         """Project several 3D problems (sp_problem records built with

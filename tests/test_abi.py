@@ -21,7 +21,8 @@ def _declared():
 def test_header_declares_the_boundary():
     names = _declared()
     for n in ("sp_create", "sp_destroy", "sp_project_tets", "sp_project_tris", "sp_project_batch",
-              "sp_sync_status", "sp_autotune", "sp_last_error"):
+              "sp_sync_status", "sp_autotune", "sp_last_error", "sp_vertex_density", "sp_tuning_set",
+              "sp_tuning_read"):
         assert n in names
 
 
@@ -118,3 +119,34 @@ def test_create_without_gpu_reports_device_error():
     out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=120)
     assert out.returncode == 0, out.stderr
     assert int(out.stdout.strip().splitlines()[-1]) == 6  # SP_E_DEVICE
+
+
+def test_vertex_density_host_validation():
+    from paper_1509_07720_amd import simproj
+
+    box = simproj.sp_grid()
+    for d in range(3):
+        box.extent[d] = 1.0
+    box.flags = 7
+    args = dict(dim=3, xyz=0x1000, n_vert=4, simplices=0x2000, n_simplex=1, mass=None, mass_uniform=1.0,
+                box=box, rho_out=0x3000, prec=simproj.SP_PREC_FP64)
+
+    def call(**kw):
+        a = dict(args, **kw)
+        return simproj.sp_vertex_density(None, a["dim"], a["xyz"], a["n_vert"], a["simplices"], a["n_simplex"],
+                                         a["mass"], a["mass_uniform"], a["box"], a["rho_out"], a["prec"])
+
+    assert call(dim=4) == simproj.SP_E_INVALID_ARG and "dim" in simproj.sp_last_error()
+    assert call(prec=9) == simproj.SP_E_INVALID_ARG
+    assert call(xyz=None) == simproj.SP_E_INVALID_ARG
+    assert call(n_simplex=-1) == simproj.SP_E_INVALID_ARG
+    assert call(mass_uniform=float("nan")) == simproj.SP_E_INVALID_ARG
+    bad = simproj.sp_grid()
+    bad.flags = simproj.SP_OUT_MASS
+    for d in range(3):
+        bad.extent[d] = 1.0
+    assert call(box=bad) == simproj.SP_E_INVALID_ARG and "SP_PERIODIC" in simproj.sp_last_error()
+    zero = simproj.sp_grid()
+    zero.flags = 1
+    assert call(box=zero) == simproj.SP_E_INVALID_ARG and "extent[0]" in simproj.sp_last_error()
+    assert call() == simproj.SP_E_INVALID_ARG and "ctx is NULL" in simproj.sp_last_error()

@@ -111,6 +111,42 @@ def test_full_size_soup_sampled_cells(ctx):
     assert abs(total - exact) <= 1e-7 * exact
 
 
+@pytest.fixture(scope="module")
+def refined_full():
+    """The 50M-tet two-level refined lattice (128^3 coarse cubes, rms
+    displacement 4 coarse cells) onto 512^3, float32-rounded."""
+    return synth.as_float32(synth.refined_3d(n=128, grid=512, sigma_cells=4.0, seed=5))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_full_size_refined_subset(ctx, refined_full, prec):
+    """Every 64th tetrahedron of the 50M-tet refined mesh onto the full 512^3
+    grid (projection is additive over simplices): every cell against the
+    oracle."""
+    sub = synth.subset(refined_full, 64)
+    ref = oracle.project(sub)
+    assert ref["stats"]["n_bad_span"] == 0
+    got, total = run(ctx, sub, prec)
+    err = oracle.cell_error(got, ref)
+    print("refined subset", prec, err, flush=True)
+    tc, tm = TOL[prec]
+    assert err["e_cell"] <= tc, err
+    assert err["e_mass"] <= tm, err
+    assert abs(total - ref["mass"].sum()) <= tm * ref["mass"].sum()
+
+
+def test_full_size_refined_total(ctx, refined_full):
+    """All 50M tetrahedra onto 512^3 in FP32C: the deposited total against
+    the exact simplex masses, and no cell below rounding level of zero (all
+    densities are positive)."""
+    got, total = run(ctx, refined_full, "fp32c")
+    exact = oracle.simplex_mass(refined_full).sum()
+    print("refined total", total, exact, flush=True)
+    assert abs(total - exact) <= 1e-7 * exact
+    assert abs(got.sum() - exact) <= 1e-7 * exact
+    assert got.min() >= -1e-6 * got.max()
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32c"])
 def test_signed_coverage_full_size(ctx, prec):
     """Per-corner rho = sign(V) on the displaced periodic lattice covers every
