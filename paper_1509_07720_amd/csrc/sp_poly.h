@@ -139,24 +139,27 @@ struct Poly3 {
         live = 0xfu;
     }
 
+    // Every slot is read (unused slots hold stale but readable values) so
+    // that the loads issue back to back instead of one per loop trip; the
+    // result is masked by `live`.
     SP_HD uint32_t below_mask(int ax, T c) const
     {
         uint32_t m = 0;
-        for (uint32_t w = live; w; w &= w - 1u) {
-            int v = lowbit(w);
-            m |= (uint32_t)(coord(v, ax) < c) << v;
-        }
-        return m;
+#pragma unroll
+        for (int v = 0; v < MAXV; ++v) m |= (uint32_t)(coord(v, ax) < c) << v;
+        return m & live;
     }
 
     SP_HD void range(int ax, T &mn, T &mx) const
     {
-        int v0 = lowbit(live);
-        mn = mx = coord(v0, ax);
-        for (uint32_t w = live & (live - 1u); w; w &= w - 1u) {
-            T c = coord(lowbit(w), ax);
-            mn = c < mn ? c : mn;
-            mx = c > mx ? c : mx;
+        const T c0 = coord(lowbit(live), ax);
+        mn = mx = c0;
+#pragma unroll
+        for (int v = 0; v < MAXV; ++v) {
+            const T c = coord(v, ax);
+            const bool in = (live >> v) & 1u;
+            mn = in && c < mn ? c : mn;
+            mx = in && c > mx ? c : mx;
         }
     }
 
@@ -274,6 +277,7 @@ struct Poly3 {
         // reached from a directed edge leaving one of its below vertices
         uint32_t un0 = live, un1 = live, un2 = live;
         int vs = 0, vcur = 0, pc = 0, cnt = 0;
+        uint32_t ncur = 0u;
         bool open = false, ba = false;
         V4<T> a;
         T e0x = 0, e0y = 0, e0z = 0, r0 = 0, epx = 0, epy = 0, epz = 0, rp = 0;
@@ -310,24 +314,29 @@ struct Poly3 {
                 cnt = 0;
                 open = true;
                 a = P(vcur);
+                ncur = N(vcur);
                 ba = (below >> vcur) & 1u;
             }
             const uint32_t bit = 1u << vcur;
             un0 &= pc == 0 ? ~bit : ~0u;
             un1 &= pc == 1 ? ~bit : ~0u;
             un2 &= pc == 2 ? ~bit : ~0u;
-            const int vnext = nbr(N(vcur), pc);
+            // the neighbour word of the current vertex is carried from the
+            // previous step, so each step waits for one round of LDS reads
+            const int vnext = nbr(ncur, pc);
             const V4<T> b = P(vnext);
+            const uint32_t nnext = N(vnext);
             const bool bb = (below >> vnext) & 1u;
             if (ba) acc(a);
             if (ba != bb) acc(ba ? isect(a, b, ax, c) : isect(b, a, ax, c));
             if (vnext == vs) {
                 open = false;
             } else {
-                const int np = slot_of(N(vnext), vcur);
+                const int np = slot_of(nnext, vcur);
                 pc = (np + 1) % 3;
                 vcur = vnext;
                 a = b;
+                ncur = nnext;
                 ba = bb;
             }
         }
