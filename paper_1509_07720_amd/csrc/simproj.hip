@@ -442,16 +442,14 @@ __global__ __launch_bounds__(WG) void k_clip(ProbDev<T> p0, Batch b, int overflo
     static_assert(WG == 64, "the queue logic assumes one wave per block");
     const ProbDev<T> &p = p0;  // fields shared by every problem of the launch
     constexpr int SLOTS = D == 3 ? MAXV : 2 * MAXP2;
-    __shared__ V4<T> s_p[SLOTS][WG];
-    __shared__ uint32_t s_nb[D == 3 ? MAXV : 1][WG];
+    __shared__ V4<T> s_p[SLOTS][WG];  // 3D: polytope slots (S4, same size); 2D: polygon buffers
     const int lane = threadIdx.x;
     const unsigned total = overflow_pass ? min(p.cs->ovf_count, (unsigned)OVF_CAP) : p.cs->total;
     unsigned *head = overflow_pass ? &p.cs->ovf_head : &p.cs->head;
     unsigned q_base = 0u, q_n = 0u, q_h = 0u;  // current chunk [q_base, q_base + q_n), next unclaimed q_h
     bool q_done = false;
     Poly3<T, MAXV, WG> P3;
-    P3.p = &s_p[0][lane];
-    P3.nb = &s_nb[0][lane];
+    P3.p = reinterpret_cast<S4<T> *>(&s_p[0][lane]);
     P3.live = 0u;
     Poly2<T, MAXP2, WG> P2;
     P2.a = &s_p[0][lane];
@@ -505,6 +503,7 @@ __global__ __launch_bounds__(WG) void k_clip(ProbDev<T> p0, Batch b, int overflo
                 if (setup_any<D>(q, sid, false, L0) == SETUP_OK) {
                     const SweepOrder ord = D == 3 ? sweep_order(L0) : kIdentity;
                     L = D == 3 ? permuted(L0, ord) : L0;
+                    if (D == 3) P3.set_density(L.v);
                     dep = make_dep<T>(q, L, ord);
                     if (overflow_pass) {
                         dep.suppress_ix = sb;

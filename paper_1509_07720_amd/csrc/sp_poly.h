@@ -23,6 +23,7 @@
 // fan triangle with the apex forms a tetrahedron whose integral is its
 // volume times the mean of its four vertex densities (Appendix C).
 #pragma once
+#include <math.h>
 #include <stdint.h>
 
 #ifndef SP_HD
@@ -66,6 +67,10 @@ SP_HD inline float sp_rcp(float x)
 #endif
 }
 SP_HD inline double sp_rcp(double x) { return 1.0 / x; }
+SP_HD inline float sp_fmin(float a, float b) { return fminf(a, b); }
+SP_HD inline float sp_fmax(float a, float b) { return fmaxf(a, b); }
+SP_HD inline double sp_fmin(double a, double b) { return fmin(a, b); }
+SP_HD inline double sp_fmax(double a, double b) { return fmax(a, b); }
 
 // Point where segment (a, b) meets the plane x_ax = c, for a strictly below
 // and b at or above the plane.  The interpolation starts from the nearer end
@@ -103,6 +108,52 @@ SP_HD inline int slot_of(uint32_t nb, int v)
 SP_HD inline uint32_t pack3(int a, int b, int c) { return (uint32_t)a | ((uint32_t)b << 8) | ((uint32_t)c << 16); }
 SP_HD inline int lowbit(uint32_t m) { return __builtin_ctz(m); }
 
+// A polytope vertex slot: position and the packed neighbour word in one
+// 16-byte (FP32) or 32-byte (FP64) record, so that a walk step reads both
+// with one load.  The density is not stored per vertex: over a simplex it
+// is an affine function of position (set once per simplex in the polytope),
+// evaluated where an integral needs it.
+template <typename T>
+struct NbBits;
+template <>
+struct NbBits<float> {
+    using type = uint32_t;
+};
+template <>
+struct NbBits<double> {
+    using type = uint64_t;
+};
+
+template <typename T>
+struct alignas(sizeof(T) * 4) S4 {
+    T x, y, z;
+    typename NbBits<T>::type nb;
+};
+static_assert(sizeof(S4<float>) == sizeof(V4<float>) && sizeof(S4<double>) == sizeof(V4<double>),
+              "polytope slots and polygon vertices share one LDS buffer");
+
+// Point where segment (a, b) meets the plane x_ax = c, for a strictly below
+// and b at or above the plane; the same rule as isect (nearer end, exact
+// coordinate along ax), positions only.
+template <typename T>
+SP_HD inline S4<T> isect3(const S4<T> &a, const S4<T> &b, int ax, T c)
+{
+    T ca = ax == 0 ? a.x : (ax == 1 ? a.y : a.z);
+    T cb = ax == 0 ? b.x : (ax == 1 ? b.y : b.z);
+    T rd = sp_rcp(cb - ca);
+    T ta = (c - ca) * rd;
+    bool from_a = ta <= T(0.5);
+    const S4<T> &s = from_a ? a : b;
+    const S4<T> &e = from_a ? b : a;
+    T t = from_a ? ta : (cb - c) * rd;
+    S4<T> q;
+    q.x = ax == 0 ? c : s.x + t * (e.x - s.x);
+    q.y = ax == 1 ? c : s.y + t * (e.y - s.y);
+    q.z = ax == 2 ? c : s.z + t * (e.z - s.z);
+    q.nb = 0;
+    return q;
+}
+
 // Vertex storage with a stride: on the GPU each lane's polytope is spread
 // over LDS with stride = lanes per block, so that lanes touching the same
 // slot hit consecutive words.  Slots in use are marked in `live`; a cut
@@ -113,14 +164,24 @@ template <typename T, int MAXV, int STRIDE>
 struct Poly3 {
     static_assert(MAXV <= 32, "vertex masks are 32-bit");
     static constexpr uint32_t SLOTS = MAXV == 32 ? 0xffffffffu : ((1u << MAXV) - 1u);
-    V4<T> *p;
-    uint32_t *nb;
+    S4<T> *p;
     uint32_t live;
+    // density rho(q) = r0 + g . (q - o) of the simplex being swept; gd is
+    // the gradient in double precision (for the one evaluation per piece
+    // that spans the whole simplex), g the same in T.  Every evaluation is
+    // clamped to [rlo, rhi], the range of the corner values: exact values
+    // inside the simplex never leave it, and for a nearly flat simplex (a
+    // huge gradient across it) the clamp bounds the effect of points that
+    // rounding puts off its plane.
+    double r0, gd[3];
+    T g[3];
+    T o[3];
+    T rlo, rhi;
 
-    SP_HD V4<T> P(int v) const { return p[v * STRIDE]; }
-    SP_HD void setP(int v, const V4<T> &q) { p[v * STRIDE] = q; }
-    SP_HD uint32_t N(int v) const { return nb[v * STRIDE]; }
-    SP_HD void setN(int v, uint32_t x) { nb[v * STRIDE] = x; }
+    SP_HD S4<T> V(int v) const { return p[v * STRIDE]; }
+    SP_HD void setV(int v, const S4<T> &q) { p[v * STRIDE] = q; }
+    SP_HD uint32_t N(int v) const { return (uint32_t)p[v * STRIDE].nb; }
+    SP_HD void setN(int v, uint32_t x) { p[v * STRIDE].nb = x; }
     SP_HD T coord(int v, int ax) const
     {
         const T *q = reinterpret_cast<const T *>(&p[v * STRIDE]);
@@ -128,14 +189,66 @@ struct Poly3 {
     }
     SP_HD bool empty() const { return live == 0u; }
 
+    // The affine density through the four corner values of a tetrahedron:
+    // g solves g . (v_k - v_0) = r_k - r_0 (Cramer's rule in FP64 on the
+    // exact differences of the corner data).
+    SP_HD void set_density(const V4<T> *v)
+    {
+        double e[3][3], dr[3];
+        for (int k = 0; k < 3; ++k) {
+            e[k][0] = (double)v[k + 1].x - (double)v[0].x;
+            e[k][1] = (double)v[k + 1].y - (double)v[0].y;
+            e[k][2] = (double)v[k + 1].z - (double)v[0].z;
+            dr[k] = (double)v[k + 1].r - (double)v[0].r;
+        }
+        double c[3][3];  // c[k] = e[k+1] x e[k+2]
+        for (int k = 0; k < 3; ++k) {
+            const double *a = e[(k + 1) % 3], *b = e[(k + 2) % 3];
+            c[k][0] = a[1] * b[2] - a[2] * b[1];
+            c[k][1] = a[2] * b[0] - a[0] * b[2];
+            c[k][2] = a[0] * b[1] - a[1] * b[0];
+        }
+        const double det = e[0][0] * c[0][0] + e[0][1] * c[0][1] + e[0][2] * c[0][2];
+        const double inv = det != 0.0 ? 1.0 / det : 0.0;
+        for (int d = 0; d < 3; ++d) {
+            gd[d] = (dr[0] * c[0][d] + dr[1] * c[1][d] + dr[2] * c[2][d]) * inv;
+            g[d] = (T)gd[d];
+        }
+        r0 = (double)v[0].r;
+        rlo = v[0].r < v[1].r ? v[0].r : v[1].r;
+        rlo = v[2].r < rlo ? v[2].r : rlo;
+        rlo = v[3].r < rlo ? v[3].r : rlo;
+        rhi = v[0].r > v[1].r ? v[0].r : v[1].r;
+        rhi = v[2].r > rhi ? v[2].r : rhi;
+        rhi = v[3].r > rhi ? v[3].r : rhi;
+        o[0] = v[0].x;
+        o[1] = v[0].y;
+        o[2] = v[0].z;
+    }
+
+    // (fmin/fmax return the other operand for a NaN, so an overflowed
+    // gradient cannot poison the sums)
+    SP_HD T clamp_rho(T r) const { return sp_fmin(sp_fmax(r, rlo), rhi); }
+
+    // density at a point, in double
+    SP_HD double rho_at(const S4<T> &q) const
+    {
+        return r0 + gd[0] * ((double)q.x - (double)o[0]) + gd[1] * ((double)q.y - (double)o[1]) +
+               gd[2] * ((double)q.z - (double)o[2]);
+    }
+
     // A positively oriented tetrahedron (det(v1-v0, v2-v0, v3-v0) > 0).
     SP_HD void init_tet(const V4<T> *v)
     {
-        for (int i = 0; i < 4; ++i) setP(i, v[i]);
-        setN(0, pack3(1, 3, 2));
-        setN(1, pack3(2, 3, 0));
-        setN(2, pack3(0, 3, 1));
-        setN(3, pack3(1, 2, 0));
+        const uint32_t nbs[4] = {pack3(1, 3, 2), pack3(2, 3, 0), pack3(0, 3, 1), pack3(1, 2, 0)};
+        for (int i = 0; i < 4; ++i) {
+            S4<T> q;
+            q.x = v[i].x;
+            q.y = v[i].y;
+            q.z = v[i].z;
+            q.nb = nbs[i];
+            setV(i, q);
+        }
         live = 0xfu;
     }
 
@@ -186,11 +299,15 @@ struct Poly3 {
         // neighbour's list then needs no edit -- or returns to the free pool.
         for (uint32_t w = gone; w; w &= w - 1u) {
             const int x = lowbit(w);
-            const uint32_t nbx = N(x);
-            const V4<T> px = P(x);
+            const S4<T> px = V(x);
+            const uint32_t nbx = (uint32_t)px.nb;
+            // the three neighbours are read together up front
+            const int v3[3] = {nbr(nbx, 0), nbr(nbx, 1), nbr(nbx, 2)};
+            const S4<T> pv3[3] = {V(v3[0]), V(v3[1]), V(v3[2])};
             bool reused = false;
+#pragma unroll
             for (int i = 0; i < 3; ++i) {
-                const int v = nbr(nbx, i);
+                const int v = v3[i];
                 if (!((keep >> v) & 1u)) continue;
                 int u;
                 if (!reused) {
@@ -202,9 +319,9 @@ struct Poly3 {
                     freem &= freem - 1u;
                 }
                 fresh |= 1u << u;
-                const V4<T> pv = P(v);
-                setP(u, keep_upper ? isect(px, pv, ax, c) : isect(pv, px, ax, c));
-                setN(u, pack3(v, v, v));
+                S4<T> q = keep_upper ? isect3(px, pv3[i], ax, c) : isect3(pv3[i], px, ax, c);
+                q.nb = pack3(v, v, v);
+                setV(u, q);
                 if (u != x) {
                     const uint32_t nbv = N(v);
                     setN(v, set_nbr(nbv, slot_of(nbv, x), u));
@@ -241,14 +358,10 @@ struct Poly3 {
         return true;
     }
 
-    // Integral of the carried density over the part below x_ax = c (or over
-    // the whole polytope when whole is true).  Returns 6*volume in s6 and
-    // 24*integral in s24 (positive for this vertex ordering).  Every directed
-    // edge is visited exactly once: a facet is walked from its first
-    // unvisited directed edge until it closes; its part below the plane is
-    // emitted in order (Sutherland-Hodgman) and fanned from its first emitted
-    // point, each fan triangle closing a tetrahedron with the apex A, a point
-    // of the cap (so the cap facet itself adds nothing).
+    // Integral of the density over the part below x_ax = c (or over the
+    // whole polytope when whole is true).  Returns 6*volume in s6 and
+    // 24*integral in s24.  Returns false if the walk does not close (a
+    // corrupted graph).
     SP_HD bool integrate_below(int ax, T c, bool whole, T &s6, T &s24) const
     {
         s6 = T(0);
@@ -257,49 +370,54 @@ struct Poly3 {
         uint32_t below = whole ? live : below_mask(ax, c);
         if (below == 0u) return true;
         if (below == live) whole = true;
-        V4<T> A = P(lowbit(live));
+        S4<T> A = V(lowbit(live));
         if (!whole) {
             bool found = false;
             for (uint32_t w = below; w && !found; w &= w - 1u) {
                 const int v = lowbit(w);
-                const uint32_t nbv = N(v);
+                const S4<T> pv = V(v);
+                const uint32_t nbv = (uint32_t)pv.nb;
                 for (int i = 0; i < 3; ++i) {
                     const int x = nbr(nbv, i);
                     if (!((below >> x) & 1u)) {
-                        A = isect(P(v), P(x), ax, c);
+                        A = isect3(pv, V(x), ax, c);
                         found = true;
                         break;
                     }
                 }
             }
         }
+        // density at the apex in double, then at each corner q as
+        // rho(A) + g . (q - A)
+        const T rA = clamp_rho((T)rho_at(A));
         // only facets holding a vertex below the plane contribute; each is
         // reached from a directed edge leaving one of its below vertices
         uint32_t un0 = live, un1 = live, un2 = live;
         int vs = 0, vcur = 0, pc = 0, cnt = 0;
         uint32_t ncur = 0u;
         bool open = false, ba = false;
-        V4<T> a;
-        T e0x = 0, e0y = 0, e0z = 0, r0 = 0, epx = 0, epy = 0, epz = 0, rp = 0;
-        auto acc = [&](const V4<T> &q) {
+        S4<T> a;
+        T e0x = 0, e0y = 0, e0z = 0, epx = 0, epy = 0, epz = 0, rf = 0, rp = 0;
+        auto acc = [&](const S4<T> &q) {
             const T ex = q.x - A.x, ey = q.y - A.y, ez = q.z - A.z;
+            const T rq = clamp_rho(rA + (g[0] * ex + g[1] * ey + g[2] * ez));
             if (cnt == 0) {
                 e0x = ex;
                 e0y = ey;
                 e0z = ez;
-                r0 = q.r;
+                rf = rq;
             } else if (cnt >= 2) {
                 const T cx = ey * epz - ez * epy;
                 const T cy = ez * epx - ex * epz;
                 const T cz = ex * epy - ey * epx;
                 const T d = e0x * cx + e0y * cy + e0z * cz;
                 s6 += d;
-                s24 += d * (A.r + r0 + q.r + rp);
+                s24 += d * (rA + rf + rp + rq);
             }
             epx = ex;
             epy = ey;
             epz = ez;
-            rp = q.r;
+            rp = rq;
             ++cnt;
         };
         const int steps = 3 * __builtin_popcount(live);
@@ -313,22 +431,22 @@ struct Poly3 {
                 vcur = v;
                 cnt = 0;
                 open = true;
-                a = P(vcur);
-                ncur = N(vcur);
+                a = V(vcur);
+                ncur = (uint32_t)a.nb;
                 ba = (below >> vcur) & 1u;
             }
             const uint32_t bit = 1u << vcur;
             un0 &= pc == 0 ? ~bit : ~0u;
             un1 &= pc == 1 ? ~bit : ~0u;
             un2 &= pc == 2 ? ~bit : ~0u;
-            // the neighbour word of the current vertex is carried from the
-            // previous step, so each step waits for one round of LDS reads
+            // the neighbour word of the current vertex comes with its
+            // position, so each step waits for one LDS read
             const int vnext = nbr(ncur, pc);
-            const V4<T> b = P(vnext);
-            const uint32_t nnext = N(vnext);
+            const S4<T> b = V(vnext);
+            const uint32_t nnext = (uint32_t)b.nb;
             const bool bb = (below >> vnext) & 1u;
             if (ba) acc(a);
-            if (ba != bb) acc(ba ? isect(a, b, ax, c) : isect(b, a, ax, c));
+            if (ba != bb) acc(ba ? isect3(a, b, ax, c) : isect3(b, a, ax, c));
             if (vnext == vs) {
                 open = false;
             } else {

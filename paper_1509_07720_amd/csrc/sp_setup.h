@@ -438,6 +438,7 @@ SP_HD inline bool sweep3(Poly3<T, MAXV, STRIDE> &P, const Local<T> &L, int sb, i
 {
     Sweep3 S;
     S.start(sb, sc, ry);
+    P.set_density(L.v);
     int r;
     while ((r = S.step(P, L, dep)) > 0) {
     }
