@@ -1,0 +1,123 @@
+// Host build of the projection's per-simplex set-up and sweep (the headers
+// the clip kernel uses), for CPU tests of their logic against the oracle:
+// the sweep over slab groups, and the overflow protocol (a sweep that runs
+// out of polytope slots reports the first piece it did not deposit; a
+// second sweep with more slots resumes there, skipping the pieces before
+// it).  Grid: origin 0, unit box, dims[d] cells, so the cell coordinate of
+// x is x * dims exactly when dims is a power of two.
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+
+#include "sp_setup.h"
+
+using namespace sp;
+
+namespace {
+
+struct HostDep {
+    double *grid;
+    int anchor[3], dims[3], periodic[3];
+    long stride[3];
+    int suppress_ix = -1, suppress_iy = 0, suppress_iz = 0;
+    long count = 0;
+    void operator()(int ix, int iy, int iz, float v)
+    {
+        if (ix == suppress_ix && (iy < suppress_iy || (iy == suppress_iy && iz < suppress_iz))) return;
+        ++count;
+        int c[3] = {anchor[0] + ix, anchor[1] + iy, anchor[2] + iz};
+        for (int d = 0; d < 3; ++d) {
+            if (periodic[d]) {
+                c[d] %= dims[d];
+                if (c[d] < 0) c[d] += dims[d];
+            } else if (c[d] < 0 || c[d] >= dims[d]) {
+                return;
+            }
+        }
+        grid[c[0] * stride[0] + c[1] * stride[1] + c[2] * stride[2]] += v;
+    }
+};
+
+template <int MAXV>
+bool sweep_from(const Local<float> &L, int sb, int sc, int ry, HostDep &dep, int *fail)
+{
+    static S4<float> slots[MAXV];
+    Poly3<float, MAXV, 1> P;
+    P.p = slots;
+    P.live = 0u;
+    return sweep3<float, MAXV, 1>(P, L, sb, sc, dep, ry, fail);
+}
+
+}  // namespace
+
+// stats: [0] skipped at set-up, [1] single-cell, [2] items, [3] items that
+// overflowed the small polytope and were resumed, [4] resumes that failed,
+// [5] pieces deposited
+extern "C" int sweep_host(const float *xyz, int64_t n_vert, const int32_t *simp, int64_t n, const float *rho,
+                          int per_corner, const int *dims, const int *periodic, int slab_group, int small_slots,
+                          double *out, long *stats)
+{
+    GridDev g;
+    memset(&g, 0, sizeof g);
+    for (int d = 0; d < 3; ++d) {
+        g.dims[d] = dims[d];
+        g.periodic[d] = periodic[d];
+        g.s_hi[d] = (float)dims[d];
+        g.scale[d] = dims[d];
+        g.extent[d] = 1.0;
+    }
+    const long stride[3] = {1, (long)dims[0], (long)dims[0] * dims[1]};
+    for (int k = 0; k < 6; ++k) stats[k] = 0;
+    for (int64_t s = 0; s < n; ++s) {
+        Local<float> L0;
+        if (setup_f32<3>(xyz, n_vert, simp, s, rho, per_corner != 0, g, true, L0) != SETUP_OK) {
+            stats[0]++;
+            continue;
+        }
+        const SweepOrder o = sweep_order(L0);
+        const Local<float> L = permuted(L0, o);
+        HostDep dep;
+        dep.grid = out;
+        for (int d = 0; d < 3; ++d) {
+            dep.anchor[d] = L.anchor[d];
+            dep.dims[d] = dims[o.ax[d]];
+            dep.periodic[d] = periodic[o.ax[d]];
+            dep.stride[d] = stride[o.ax[d]];
+        }
+        if (L0.span[0] == 1 && L0.span[1] == 1 && L0.span[2] == 1) {
+            stats[1]++;
+            HostDep d0 = dep;
+            for (int d = 0; d < 3; ++d) {
+                d0.anchor[d] = L0.anchor[d];
+                d0.dims[d] = dims[d];
+                d0.periodic[d] = periodic[d];
+                d0.stride[d] = stride[d];
+            }
+            d0(0, 0, 0, L0.det * (L0.v[0].r + L0.v[1].r + L0.v[2].r + L0.v[3].r) / 24.0f);
+            stats[5]++;
+            continue;
+        }
+        const int sx = L.span[0];
+        const int nit = (sx + slab_group - 1) / slab_group, per = (sx + nit - 1) / nit;
+        for (int k = 0; k < nit; ++k) {
+            const int sb = k * per, sc = sx - sb < per ? sx - sb : per;
+            if (sc <= 0) continue;
+            stats[2]++;
+            int fail[3];
+            HostDep d1 = dep;
+            const bool ok = small_slots ? sweep_from<10>(L, sb, sc, 0, d1, fail) : sweep_from<18>(L, sb, sc, 0, d1, fail);
+            stats[5] += d1.count;
+            if (ok) continue;
+            // resume with room to spare from the first piece not deposited
+            stats[3]++;
+            HostDep d2 = dep;
+            d2.suppress_ix = fail[0];
+            d2.suppress_iy = fail[1];
+            d2.suppress_iz = fail[2];
+            int fail2[3];
+            if (!sweep_from<32>(L, fail[0], sb + sc - fail[0], fail[1], d2, fail2)) stats[4]++;
+            stats[5] += d2.count;
+        }
+    }
+    return 0;
+}
