@@ -156,6 +156,39 @@ def batch_leg(ctx, steps, warmup):
     return res
 
 
+def vertex_density_leg(ctx, steps, warmup):
+    """The per-vertex density estimate on the 64^3 Zel'dovich lattice (1.57M
+    tets, 262,144 vertices), FP32 and FP64 inputs, equal masses."""
+    import torch
+
+    from paper_1509_07720_amd import synth
+
+    prob = synth.zeldovich_3d(n=64, grid=128, sigma_cells=1.5, seed=2)
+    dev = torch.device("cuda:0")
+    simp = torch.tensor(np.asarray(prob["simplices"]), dtype=torch.int32, device=dev)
+    ns, nv = simp.shape[0], prob["xyz"].shape[0]
+    res = {"workload": "zeldovich-64^3-lattice", "n_simplex": ns, "n_vert": nv}
+    for prec, dt, b in (("fp32c", torch.float32, 4), ("fp64", torch.float64, 8)):
+        xyz = torch.tensor(np.asarray(prob["xyz"]), dtype=dt, device=dev)
+        out = torch.empty(nv, dtype=dt, device=dev)
+        for _ in range(warmup):
+            ctx.vertex_density(xyz, simp, None, 1.0 / ns, precision=prec, out=out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ctx.vertex_density(xyz, simp, None, 1.0 / ns, precision=prec, out=out)
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / steps
+        # connectivity once, each corner's coordinates, vertex output, the
+        # two FP64 accumulators per vertex (zeroed, then read)
+        algo = ns * 16 + ns * 4 * 3 * b + nv * b + nv * 16 * 2
+        res[prec] = {"ms": sec * 1e3, "simplices_per_s": ns / sec, "algorithmic_bytes": algo,
+                     "hbm_gbs": algo / sec / 1e9, "hbm_frac": algo / sec / 1e9 / PEAK_HBM_GBS,
+                     "fp64_atomics_per_s": ns * 4 * 2 / sec}
+        log(f"vertex density {prec}: {sec * 1e3:.3f} ms ({ns / sec:.3e} tets/s)")
+    return res
+
+
 def time_steps(ctx, args_dev, steps, warmup, prec):
     import torch
 
@@ -187,6 +220,7 @@ def main() -> int:
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--batch", action="store_true", help="also time the 64-problem batched workload")
     ap.add_argument("--no-atomic-peak", action="store_true", help="skip the atomic-rate measurement (mbench)")
+    ap.add_argument("--no-vertex-density", action="store_true", help="skip the per-vertex density leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (--gpus must be 1)", file=sys.stderr)
@@ -252,6 +286,7 @@ def main() -> int:
         del xyz64, rho64, out64
 
     batch = batch_leg(ctx, max(1, min(args.steps, 3)), 1) if args.batch else None
+    vdens = None if args.no_vertex_density else vertex_density_leg(ctx, max(1, args.steps), 1)
 
     traffic, traffic_src = clip_traffic()
     deposits_per_s = pieces / (clip_ms * 1e-3)
@@ -302,6 +337,7 @@ def main() -> int:
                      "atomic": {"deposits_per_s": deposits_per_s, "measured_peak_per_s": apeak,
                                 "frac": deposits_per_s / apeak if apeak else None}},
         "batch": batch,
+        "vertex_density": vdens,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

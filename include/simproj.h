@@ -123,6 +123,28 @@ sp_status sp_project_tets(sp_ctx *ctx, const sp_problem *prob, sp_precision prec
  * paper's 2D, i.e. 4D phase-space, case; Section 3.1 eq. eq:E02D). */
 sp_status sp_project_tris(sp_ctx *ctx, const sp_problem *prob, sp_precision prec, void *stream);
 
+/* Accuracy-controlled projection of tetrahedra (Section 3.4, eq. eq_accuracy
+ * and eq_accuracy2, and the per-voxel control the paper describes after its
+ * Table 1).  The problem is projected in FP32C while the largest |contribution|
+ * C_max of every cell is recorded; a cell whose sum P satisfies
+ *     |P| < C_max * 2^(wrong_bits + accurate_bits - 23)
+ * may have fewer than `accurate_bits` correct bits when each FP32
+ * contribution has up to `wrong_bits` wrong trailing bits of its 23.  Those
+ * cells are flagged, every simplex whose bounding box holds a flagged cell is
+ * projected again in FP64, and the FP64 sums replace the flagged cells (as
+ * out + out_lo when the caller keeps out_lo).  With non-negative densities
+ * P >= C_max and nothing is flagged; the control matters where signed
+ * densities cancel.
+ *   prob           as for sp_project_tets with SP_PREC_FP32C; SP_ACCUMULATE is
+ *                  rejected (SP_E_INVALID_ARG)
+ *   accurate_bits  1..40;  wrong_bits  0..23 (the paper's W)
+ *   counts         optional HOST int64[2]: flagged cells, re-projected simplices
+ * Synchronises with `stream` once (after flagging, to size the FP64 pass);
+ * uses context-owned buffers of about 19 bytes per cell plus, when cells are
+ * flagged, 24 bytes per vertex and 48 per re-projected simplex. */
+sp_status sp_project_tets_accurate(sp_ctx *ctx, const sp_problem *prob, int accurate_bits, int wrong_bits,
+                                   int64_t *counts, void *stream);
+
 /* Project n independent problems of dimension `dim` (3 only in this build;
  * 1 <= n <= 65535, n == 0 is a no-op) in one persistent, work-stealing
  * launch; `probs` is a HOST array of n problems whose buffers are device

@@ -88,6 +88,7 @@ __device__ inline void record_error(ErrState *e, int code)
 struct DepF32 {
     float *hi;
     float *lo;
+    uint32_t *cmax;  // optional: largest |contribution| per cell, as float bits
     int anchor[3];   // along the sweep axes
     int dims[3];
     int periodic[3];
@@ -112,6 +113,7 @@ struct DepF32 {
         }
         size_t idx = (size_t)c[0] * stride[0] + (size_t)c[1] * stride[1] + (size_t)c[2] * stride[2];
         float x = v * scale;
+        if (cmax) atomicMax(cmax + idx, __float_as_uint(fabsf(x)));
         float old = unsafeAtomicAdd(hi + idx, x);
         float s = old + x;
         float bb = s - old;
@@ -184,6 +186,7 @@ struct ProbDev {
     ErrState *es;
     int slab_group;
     int count_pieces;
+    uint32_t *cmax;  // FP32C: per-cell largest contribution (accuracy control), or NULL
 };
 
 // Several problems in one launch: their descriptors in device memory and,
@@ -241,6 +244,7 @@ __device__ inline DepF32 make_dep<float>(const ProbDev<float> &p, const Local<fl
     DepF32 d;
     d.hi = p.out;
     d.lo = p.lo;
+    d.cmax = p.cmax;
     const size_t s1 = (size_t)p.g.dims[0], s2 = (size_t)p.g.dims[0] * (size_t)p.g.dims[1];
     for (int k = 0; k < 3; ++k) {
         d.dims[k] = sel3(p.g.dims[0], p.g.dims[1], p.g.dims[2], o.ax[k]);
@@ -622,6 +626,89 @@ __global__ __launch_bounds__(256) void k_vd_finish(const double *acc, int64_t n_
     rho[j] = den > 0.0 ? (T)(num / den) : T(0);
 }
 
+// Per-voxel accuracy control (Section 3.4, eq. eq_accuracy and
+// eq_accuracy2): a cell whose sum P has a binary exponent below
+// e_max - S + W + A (e_max: the largest contribution's exponent; S the
+// significand bits of the arithmetic, W the bits a contribution may have
+// wrong, A the bits wanted) is flagged, the simplices touching flagged cells
+// are re-projected at higher precision, and their values replace the
+// flagged cells'.  Here the test is |P| < max|C| * 2^(W + A - S), S = 23.
+__global__ __launch_bounds__(256) void k_flag(const float *hi, const float *lo, const uint32_t *cmax, size_t ncell,
+                                              float factor, uint8_t *flags, unsigned long long *nflag)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ncell) return;
+    const float cm = __uint_as_float(cmax[i]);
+    const double P = (double)hi[i] + (double)lo[i];
+    const bool f = cm > 0.0f && fabs(P) < (double)cm * (double)factor;
+    flags[i] = f ? 1 : 0;
+    if (f) atomicAdd(nflag, 1ull);
+}
+
+// Simplices whose bounding box holds a flagged cell (boxes of more than
+// 4096 cells are taken without looking).
+__global__ __launch_bounds__(256) void k_tag(ProbDev<float> p, const uint8_t *flags, int32_t *list,
+                                             unsigned long long *ntag)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= p.n) return;
+    Local<float> L;
+    if (setup_any<3>(p, s, false, L) != SETUP_OK) return;
+    const int sx = L.span[0], sy = L.span[1], sz = L.span[2];
+    bool hit = (int64_t)sx * sy * sz > 4096;
+    for (int k = 0; k < sz && !hit; ++k) {
+        int cz = L.anchor[2] + k;
+        if (p.g.periodic[2]) cz = wrap_index(cz, p.g.dims[2]);
+        else if (cz < 0 || cz >= p.g.dims[2]) continue;
+        for (int j = 0; j < sy && !hit; ++j) {
+            int cy = L.anchor[1] + j;
+            if (p.g.periodic[1]) cy = wrap_index(cy, p.g.dims[1]);
+            else if (cy < 0 || cy >= p.g.dims[1]) continue;
+            for (int i = 0; i < sx && !hit; ++i) {
+                int cx = L.anchor[0] + i;
+                if (p.g.periodic[0]) cx = wrap_index(cx, p.g.dims[0]);
+                else if (cx < 0 || cx >= p.g.dims[0]) continue;
+                const size_t idx = ((size_t)cz * p.g.dims[1] + cy) * p.g.dims[0] + cx;
+                hit = flags[idx] != 0;
+            }
+        }
+    }
+    if (hit) list[atomicAdd(ntag, 1ull)] = (int32_t)s;
+}
+
+// The tagged simplices as an FP64 problem: all vertices widened to double,
+// the tagged simplices' connectivity and per-corner densities compacted.
+__global__ __launch_bounds__(256) void k_widen(const float *x, size_t n, double *y)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = (double)x[i];
+}
+
+__global__ __launch_bounds__(256) void k_gather_tagged(ProbDev<float> p, const int32_t *list, int64_t ntag,
+                                                       int32_t *simp, double *rho)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ntag) return;
+    const int64_t s = list[t];
+    for (int a = 0; a < 4; ++a) {
+        const int32_t v = p.simp[s * 4 + a];
+        simp[t * 4 + a] = v;
+        rho[t * 4 + a] = (double)(p.per_corner ? p.rho[s * 4 + a] : p.rho[v]);
+    }
+}
+
+// Flagged cells take the FP64 value, split into hi + lo.
+__global__ __launch_bounds__(256) void k_patch(float *hi, float *lo, const uint8_t *flags, const double *val,
+                                               size_t ncell)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ncell || !flags[i]) return;
+    const double v = val[i];
+    const float h = (float)v;
+    hi[i] = h;
+    lo[i] = (float)(v - (double)h);
+}
+
 // hi + lo -> out (unless the caller keeps lo), FP64 total of the grid in mass
 // units.
 template <typename T>
@@ -675,6 +762,11 @@ struct sp_ctx {
     // captured batched launches, by problem signature
     hipStream_t cap_stream;
     std::vector<struct GraphEntry> graphs;
+    // buffers of the accuracy-controlled projection (grown on demand)
+    struct Buf {
+        void *p = nullptr;
+        size_t cap = 0;
+    } aux[2];
 };
 
 struct GraphEntry {
@@ -789,6 +881,8 @@ extern "C" void sp_destroy(sp_ctx *ctx)
     drop_events(ctx);
     drop_graphs(ctx);
     (void)hipStreamDestroy(ctx->cap_stream);
+    for (auto &b : ctx->aux)
+        if (b.p) (void)hipFree(b.p);
     if (ctx->scratch) (void)hipFree(ctx->scratch);
     (void)hipFree(ctx->cs);
     delete ctx;
@@ -797,6 +891,22 @@ extern "C" void sp_destroy(sp_ctx *ctx)
 extern "C" const char *sp_last_error(const sp_ctx *)
 {
     return g_err.c_str();
+}
+
+static sp_status ensure_buf(sp_ctx::Buf &b, size_t bytes)
+{
+    if (bytes <= b.cap) return SP_OK;
+    HIPCHECK(hipDeviceSynchronize());
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.cap = 0;
+    const size_t want = bytes + bytes / 4;
+    if (hipMalloc(&b.p, want) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(SP_E_NO_MEMORY, "buffer allocation of %zu bytes failed", want);
+    }
+    b.cap = want;
+    return SP_OK;
 }
 
 static sp_status ensure_scratch(sp_ctx *ctx, size_t bytes)
@@ -962,6 +1072,7 @@ static sp_status prepare(sp_ctx *ctx, const sp_problem *probs, int n, std::vecto
         p.es = ctx->es;
         p.slab_group = ctx->tune.slab_group;
         p.count_pieces = ctx->profiling >= 2;
+        p.cmax = nullptr;
     }
     return SP_OK;
 }
@@ -1065,6 +1176,119 @@ extern "C" sp_status sp_project_tris(sp_ctx *ctx, const sp_problem *prob, sp_pre
     if (!ctx) return fail(SP_E_INVALID_ARG, "ctx is NULL");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     return prec == SP_PREC_FP32C ? project_impl<2, float>(ctx, prob, s) : project_impl<2, double>(ctx, prob, s);
+}
+
+// Accuracy-controlled projection (Section 3.4): FP32C projection with the
+// largest contribution of every cell recorded, flag the cells whose sum may
+// have fewer than `accurate_bits` correct bits, re-project in FP64 the
+// simplices that touch them, and replace the flagged cells.
+extern "C" sp_status sp_project_tets_accurate(sp_ctx *ctx, const sp_problem *prob, int accurate_bits,
+                                              int wrong_bits, int64_t *counts, void *stream)
+{
+    sp_status st = check_problem(prob, 3, SP_PREC_FP32C);
+    if (st != SP_OK) return st;
+    if (prob->grid.flags & SP_ACCUMULATE) return fail(SP_E_INVALID_ARG, "SP_ACCUMULATE is not supported here");
+    if (accurate_bits < 1 || accurate_bits > 40) return fail(SP_E_INVALID_ARG, "accurate_bits %d not in 1..40", accurate_bits);
+    if (wrong_bits < 0 || wrong_bits > 23) return fail(SP_E_INVALID_ARG, "wrong_bits %d not in 0..23", wrong_bits);
+    if (!ctx) return fail(SP_E_INVALID_ARG, "ctx is NULL");
+    HIPCHECK(hipSetDevice(ctx->device));
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    size_t ncell = 1;
+    for (int d = 0; d < 3; ++d) ncell *= (size_t)prob->grid.dims[d];
+    const int64_t n = prob->n_simplex;
+    const bool own_lo = prob->out_lo == nullptr;
+    // phase-1 buffers: low grid (unless the caller's), largest contribution,
+    // flags, two counters, tag list, FP64 patch grid
+    size_t off = 0;
+    const size_t o_lo = off;
+    off = align_up(off + (own_lo ? sizeof(float) * ncell : 0));
+    const size_t o_cmax = off;
+    off = align_up(off + sizeof(uint32_t) * ncell);
+    const size_t o_flag = off;
+    off = align_up(off + ncell);
+    const size_t o_cnt = off;
+    off = align_up(off + 2 * sizeof(unsigned long long));
+    const size_t o_list = off;
+    off = align_up(off + sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    const size_t o_patch = off;
+    off = align_up(off + sizeof(double) * ncell);
+    st = ensure_buf(ctx->aux[0], off);
+    if (st != SP_OK) return st;
+    char *base = static_cast<char *>(ctx->aux[0].p);
+    float *lo = own_lo ? reinterpret_cast<float *>(base + o_lo) : prob->out_lo;
+    uint32_t *cmax = reinterpret_cast<uint32_t *>(base + o_cmax);
+    uint8_t *flags = reinterpret_cast<uint8_t *>(base + o_flag);
+    unsigned long long *cnt = reinterpret_cast<unsigned long long *>(base + o_cnt);
+    int32_t *list = reinterpret_cast<int32_t *>(base + o_list);
+    double *patch = reinterpret_cast<double *>(base + o_patch);
+
+    // 1. FP32C projection into out + lo (both kept), largest contribution per cell
+    sp_problem p1 = *prob;
+    p1.out_lo = lo;
+    p1.total_mass = nullptr;
+    std::vector<Prepared<float>> v;
+    int64_t ntotal = 0;
+    st = prepare<3, float>(ctx, &p1, 1, v, ntotal);
+    if (st != SP_OK) return st;
+    v[0].p.cmax = cmax;
+    hipLaunchKernelGGL(k_fill<uint32_t>, dim3(grid_blocks(ncell, 256)), dim3(256), 0, s, cmax, ncell);
+    hipLaunchKernelGGL(k_fill<unsigned long long>, dim3(1), dim3(64), 0, s, cnt, (size_t)2);
+    Batch nb = {nullptr, nullptr, 0};
+    enqueue<3, float>(ctx, v, nb, (ntotal + 255) / 256, s, false);
+    // 2. flags and tags
+    const float factor = ldexpf(1.0f, wrong_bits + accurate_bits - 23);
+    hipLaunchKernelGGL(k_flag, dim3(grid_blocks(ncell, 256)), dim3(256), 0, s, (const float *)prob->out,
+                       (const float *)lo, (const uint32_t *)cmax, ncell, factor, flags, cnt);
+    if (n > 0)
+        hipLaunchKernelGGL(k_tag, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, v[0].p, (const uint8_t *)flags,
+                           list, cnt + 1);
+    unsigned long long hc[2] = {0, 0};
+    HIPCHECK(hipMemcpyAsync(hc, cnt, sizeof hc, hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    const int64_t ntag = (int64_t)hc[1];
+    // 3. FP64 re-projection of the tagged simplices, patched into the flagged cells
+    if (ntag > 0) {
+        const size_t nx = 3 * (size_t)prob->n_vert;
+        const size_t q_x = 0;
+        const size_t q_s = align_up(q_x + sizeof(double) * nx);
+        const size_t q_r = align_up(q_s + sizeof(int32_t) * 4 * (size_t)ntag);
+        const size_t q_end = align_up(q_r + sizeof(double) * 4 * (size_t)ntag);
+        st = ensure_buf(ctx->aux[1], q_end);
+        if (st != SP_OK) return st;
+        char *b2 = static_cast<char *>(ctx->aux[1].p);
+        double *x64 = reinterpret_cast<double *>(b2 + q_x);
+        int32_t *simp = reinterpret_cast<int32_t *>(b2 + q_s);
+        double *rho = reinterpret_cast<double *>(b2 + q_r);
+        hipLaunchKernelGGL(k_widen, dim3(grid_blocks(nx, 256)), dim3(256), 0, s, (const float *)prob->xyz, nx, x64);
+        hipLaunchKernelGGL(k_gather_tagged, dim3((unsigned)((ntag + 255) / 256)), dim3(256), 0, s, v[0].p,
+                           (const int32_t *)list, ntag, simp, rho);
+        sp_problem p2;
+        memset(&p2, 0, sizeof p2);
+        p2.xyz = x64;
+        p2.n_vert = prob->n_vert;
+        p2.simplices = simp;
+        p2.n_simplex = ntag;
+        p2.rho = rho;
+        p2.grid = prob->grid;
+        p2.grid.flags = (prob->grid.flags & (SP_PERIODIC_X | SP_PERIODIC_Y | SP_PERIODIC_Z | SP_OUT_MASS)) |
+                        SP_RHO_PER_CORNER;
+        p2.out = patch;
+        st = project_impl<3, double>(ctx, &p2, s);
+        if (st != SP_OK) return st;
+        hipLaunchKernelGGL(k_patch, dim3(grid_blocks(ncell, 256)), dim3(256), 0, s, (float *)prob->out, lo,
+                           (const uint8_t *)flags, (const double *)patch, ncell);
+    }
+    // 4. merge (unless the caller keeps the low grid) and the FP64 total
+    if (prob->total_mass) hipLaunchKernelGGL(k_fill<double>, dim3(1), dim3(64), 0, s, prob->total_mass, (size_t)1);
+    hipLaunchKernelGGL(k_finalize<float>, dim3(grid_blocks(ncell, 256 * 8)), dim3(256), 0, s, (float *)prob->out, lo,
+                       own_lo ? 0 : 1, ncell, v[0].to_mass, prob->total_mass);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(SP_E_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+    if (counts) {
+        counts[0] = (int64_t)hc[0];
+        counts[1] = ntag;
+    }
+    return SP_OK;
 }
 
 // FNV-1a over the bytes that determine a batched launch.

@@ -73,6 +73,9 @@ _lib.sp_destroy.restype = None
 for _name in ("sp_project_tets", "sp_project_tris"):
     getattr(_lib, _name).argtypes = [_V, ctypes.POINTER(sp_problem), ctypes.c_int, _V]
     getattr(_lib, _name).restype = ctypes.c_int
+_lib.sp_project_tets_accurate.argtypes = [_V, ctypes.POINTER(sp_problem), ctypes.c_int, ctypes.c_int,
+                                          ctypes.POINTER(ctypes.c_int64), _V]
+_lib.sp_project_tets_accurate.restype = ctypes.c_int
 _lib.sp_project_batch.argtypes = [_V, ctypes.c_int, ctypes.POINTER(sp_problem), ctypes.c_int, ctypes.c_int, _V]
 _lib.sp_project_batch.restype = ctypes.c_int
 _lib.sp_sync_status.argtypes = [_V, _V]
@@ -127,6 +130,12 @@ def sp_project_tets(ctx, prob: sp_problem, prec: int, stream=None) -> int:
 
 def sp_project_tris(ctx, prob: sp_problem, prec: int, stream=None) -> int:
     return _lib.sp_project_tris(ctx, ctypes.byref(prob), int(prec), stream)
+
+
+def sp_project_tets_accurate(ctx, prob: sp_problem, accurate_bits: int, wrong_bits: int, stream=None):
+    counts = (ctypes.c_int64 * 2)()
+    st = _lib.sp_project_tets_accurate(ctx, ctypes.byref(prob), int(accurate_bits), int(wrong_bits), counts, stream)
+    return st, counts[0], counts[1]
 
 
 def sp_project_batch(ctx, dim: int, probs: Sequence[sp_problem], prec: int, stream=None) -> int:
@@ -294,6 +303,28 @@ class Context:
                                out.data_ptr() if out.numel() else None, prec, _stream_ptr(stream))
         _check(st, "sp_vertex_density")
         return out
+
+    def project_accurate(self, xyz, simplices, rho, dims, accurate_bits: int = 10, wrong_bits: int = 10,
+                         origin=(0.0, 0.0, 0.0), extent=(1.0, 1.0, 1.0), periodic=(True, True, True),
+                         rho_per_corner: bool = False, out=None, out_lo=None, out_mass: bool = False,
+                         validate: bool = False, want_total: bool = True, stream=None):
+        """FP32C projection with per-voxel accuracy control
+        (sp_project_tets_accurate); returns (grid, total_mass, flagged_cells,
+        reprojected_simplices)."""
+        import torch
+
+        for t, dt in ((xyz, torch.float32), (rho, torch.float32), (simplices, torch.int32)):
+            if t.dtype != dt or not t.is_cuda or not t.is_contiguous():
+                raise TypeError("xyz/rho must be contiguous float32 and simplices int32 device tensors")
+        shape = tuple(int(d) for d in reversed(list(dims)[:3]))
+        if out is None:
+            out = torch.empty(shape, dtype=torch.float32, device=xyz.device)
+        total = torch.zeros(1, dtype=torch.float64, device=xyz.device) if want_total else None
+        p = make_problem(xyz, simplices, rho, dims, origin, extent, periodic, rho_per_corner, out, out_lo, total,
+                         out_mass, False, validate)
+        st, nflag, ntag = sp_project_tets_accurate(self.handle, p, accurate_bits, wrong_bits, _stream_ptr(stream))
+        _check(st, "sp_project_tets_accurate")
+        return out, total, nflag, ntag
 
     def project_batch(self, problems, precision: str = "fp32c", stream=None) -> None:
         """Project several 3D problems (sp_problem records built with

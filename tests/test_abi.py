@@ -22,7 +22,7 @@ def test_header_declares_the_boundary():
     names = _declared()
     for n in ("sp_create", "sp_destroy", "sp_project_tets", "sp_project_tris", "sp_project_batch",
               "sp_sync_status", "sp_autotune", "sp_last_error", "sp_vertex_density", "sp_tuning_set",
-              "sp_tuning_read"):
+              "sp_tuning_read", "sp_project_tets_accurate"):
         assert n in names
 
 
@@ -150,3 +150,18 @@ def test_vertex_density_host_validation():
     zero.flags = 1
     assert call(box=zero) == simproj.SP_E_INVALID_ARG and "extent[0]" in simproj.sp_last_error()
     assert call() == simproj.SP_E_INVALID_ARG and "ctx is NULL" in simproj.sp_last_error()
+
+
+def test_accurate_host_validation():
+    from paper_1509_07720_amd import simproj
+
+    p = _prob()
+    st, _, _ = simproj.sp_project_tets_accurate(None, p, 10, 10)
+    assert st == simproj.SP_E_INVALID_ARG and "ctx is NULL" in simproj.sp_last_error()
+    for a, w, needle in ((0, 10, "accurate_bits"), (41, 10, "accurate_bits"), (10, -1, "wrong_bits"),
+                         (10, 24, "wrong_bits")):
+        st, _, _ = simproj.sp_project_tets_accurate(None, p, a, w)
+        assert st == simproj.SP_E_INVALID_ARG and needle in simproj.sp_last_error()
+    p.grid.flags |= simproj.SP_ACCUMULATE
+    st, _, _ = simproj.sp_project_tets_accurate(None, p, 10, 10)
+    assert st == simproj.SP_E_INVALID_ARG and "SP_ACCUMULATE" in simproj.sp_last_error()
