@@ -9,9 +9,12 @@ deposits, clip-integrate-deposit of every other simplex, and the hi+lo merge
 with the FP64 total-mass reduction.  Inputs are resident in HBM before the
 timed region.  The same workload is also timed in FP64 mode.
 
-With --batch, the batched workload (64 Zel'dovich meshes of 1e4..2e6 tets
-onto grids of 32^3..256^3) is also timed: one captured graph launch for all
-64 problems against 64 sequential calls, in FP32C and FP64.
+Also reported (not part of `value`): the per-vertex density estimate on the
+64^3 lattice, and the accuracy-controlled projection of cancelling densities
+against plain FP32C and FP64.  With --batch, the batched workload (64
+Zel'dovich meshes of 1e4..2e6 tets onto grids of 32^3..256^3) is also timed:
+one captured graph launch for all 64 problems against 64 sequential calls,
+in FP32C and FP64.
 
 Prints one JSON line (see the "metric" field).  --gpus above 1 is refused:
 this build measures one GPU.
@@ -189,6 +192,50 @@ def vertex_density_leg(ctx, steps, warmup):
     return res
 
 
+def accuracy_leg(ctx, steps, warmup):
+    """Per-voxel accuracy control on cancelling densities: the 64^3 Zel'dovich
+    sheet plus, over half of it, a copy displaced by 1e-4 of its displacement
+    with the opposite density, onto 128^3.  Times the plain FP32C call, the
+    accuracy-controlled call (A = 12, W = 10) and the plain FP64 call."""
+    import torch
+
+    from paper_1509_07720_amd import synth
+
+    a = synth.zeldovich_3d(n=64, grid=128, sigma_cells=1.5, seed=21)
+    b = synth.zeldovich_3d(n=64, grid=128, sigma_cells=1.5 * (1.0 + 1e-4), seed=21)
+    nb = b["simplices"].shape[0] // 2
+    nv = a["xyz"].shape[0]
+    xyz = np.vstack([a["xyz"], b["xyz"]])
+    simp = np.vstack([a["simplices"], b["simplices"][:nb] + nv]).astype(np.int32)
+    rho = np.concatenate([a["rho"], -b["rho"]])
+    dev = torch.device("cuda:0")
+    s = torch.tensor(simp, dtype=torch.int32, device=dev)
+    x32, r32 = torch.tensor(xyz, dtype=torch.float32, device=dev), torch.tensor(rho, dtype=torch.float32, device=dev)
+    x64, r64 = x32.double(), r32.double()
+    dims = [128] * 3
+    res = {"workload": "cancelling-zeldovich-sheets-64^3(+half)-to-128^3", "n_simplex": int(simp.shape[0]),
+           "accurate_bits": 12, "wrong_bits": 10}
+    runs = {
+        "fp32c": lambda: ctx.project(x32, s, r32, dims, precision="fp32c", out_mass=True),
+        "accurate": lambda: ctx.project_accurate(x32, s, r32, dims, accurate_bits=12, wrong_bits=10, out_mass=True),
+        "fp64": lambda: ctx.project(x64, s, r64, dims, precision="fp64", out_mass=True),
+    }
+    for name, fn in runs.items():
+        for _ in range(warmup):
+            out = fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            out = fn()
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / steps
+        res[name] = {"ms": sec * 1e3, "simplices_per_s": simp.shape[0] / sec}
+        if name == "accurate":
+            res[name]["flagged_cells"], res[name]["reprojected_simplices"] = int(out[2]), int(out[3])
+        log(f"accuracy leg {name}: {sec * 1e3:.2f} ms")
+    return res
+
+
 def time_steps(ctx, args_dev, steps, warmup, prec):
     import torch
 
@@ -221,6 +268,7 @@ def main() -> int:
     ap.add_argument("--batch", action="store_true", help="also time the 64-problem batched workload")
     ap.add_argument("--no-atomic-peak", action="store_true", help="skip the atomic-rate measurement (mbench)")
     ap.add_argument("--no-vertex-density", action="store_true", help="skip the per-vertex density leg")
+    ap.add_argument("--no-accuracy", action="store_true", help="skip the accuracy-control leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (--gpus must be 1)", file=sys.stderr)
@@ -287,6 +335,7 @@ def main() -> int:
 
     batch = batch_leg(ctx, max(1, min(args.steps, 3)), 1) if args.batch else None
     vdens = None if args.no_vertex_density else vertex_density_leg(ctx, max(1, args.steps), 1)
+    accur = None if args.no_accuracy else accuracy_leg(ctx, max(1, min(args.steps, 5)), 1)
 
     traffic, traffic_src = clip_traffic()
     deposits_per_s = pieces / (clip_ms * 1e-3)
@@ -338,6 +387,7 @@ def main() -> int:
                                 "frac": deposits_per_s / apeak if apeak else None}},
         "batch": batch,
         "vertex_density": vdens,
+        "accuracy_control": accur,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
