@@ -145,10 +145,10 @@ sp_status sp_project_tris(sp_ctx *ctx, const sp_problem *prob, sp_precision prec
 sp_status sp_project_tets_accurate(sp_ctx *ctx, const sp_problem *prob, int accurate_bits, int wrong_bits,
                                    int64_t *counts, void *stream);
 
-/* Project n independent problems of dimension `dim` (3 only in this build;
- * 1 <= n <= 65535, n == 0 is a no-op) in one persistent, work-stealing
+/* Project n independent problems of dimension `dim` (2 or 3; 1 <= n <=
+ * 65535, n == 0 is a no-op) in one persistent, work-stealing
  * launch; `probs` is a HOST array of n problems whose buffers are device
- * pointers, each problem as in sp_project_tets (flags, out_lo and
+ * pointers, each problem as in sp_project_tets / sp_project_tris (flags, out_lo and
  * total_mass per problem; their output grids must not overlap).  The work
  * items of all problems are ordered by estimated cost in one list, so the
  * load is balanced across problems (the cost-based balancing the paper

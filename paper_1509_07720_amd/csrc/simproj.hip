@@ -856,10 +856,10 @@ extern "C" sp_status sp_create(int hip_device, sp_ctx **ctx)
     c->dummy_total = reinterpret_cast<double *>(reinterpret_cast<char *>(st) + 2048);
     (void)hipMemset(st, 0, 4096);
     (void)hipDeviceSynchronize();
-    c->tune.slab_group = 4;
+    c->tune.slab_group = 8;
     c->tune.chunks_per_cu = 0;
     // launch-shape overrides for tuning experiments
-    if (const char *e = getenv("SIMPROJ_SLAB_GROUP")) c->tune.slab_group = atoi(e) > 0 ? atoi(e) : 4;
+    if (const char *e = getenv("SIMPROJ_SLAB_GROUP")) c->tune.slab_group = atoi(e) > 0 ? atoi(e) : 8;
     if (const char *e = getenv("SIMPROJ_CLIP_BLOCKS_PER_CU")) c->tune.chunks_per_cu = atoi(e) > 0 ? atoi(e) : 0;
     c->profiling = 0;
     c->prof_calls = 0;
@@ -1302,15 +1302,17 @@ static uint64_t fnv(uint64_t h, const void *data, size_t n)
     return h;
 }
 
-template <typename T>
+template <int D, typename T>
 static sp_status batch_impl(sp_ctx *ctx, const sp_problem *probs, int n, sp_precision prec, hipStream_t stream)
 {
     HIPCHECK(hipSetDevice(ctx->device));
     std::vector<Prepared<T>> v;
     int64_t ntotal = 0;
-    sp_status st = prepare<3, T>(ctx, probs, n, v, ntotal);
+    sp_status st = prepare<D, T>(ctx, probs, n, v, ntotal);
     if (st != SP_OK) return st;
     uint64_t key = 1469598103934665603ull;
+    const int dim = D;
+    key = fnv(key, &dim, sizeof dim);
     key = fnv(key, &prec, sizeof prec);
     key = fnv(key, &n, sizeof n);
     key = fnv(key, probs, sizeof(sp_problem) * (size_t)n);
@@ -1345,7 +1347,7 @@ static sp_status batch_impl(sp_ctx *ctx, const sp_problem *probs, int n, sp_prec
         // capture the whole launch sequence once; replays cost one launch
         hipGraph_t graph = nullptr;
         HIPCHECK(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
-        enqueue<3, T>(ctx, v, b, boffs[n], ctx->cap_stream, false);
+        enqueue<D, T>(ctx, v, b, boffs[n], ctx->cap_stream, false);
         hipError_t e1 = hipStreamEndCapture(ctx->cap_stream, &graph);
         if (e1 != hipSuccess) {
             (void)hipFree(g.dev);
@@ -1370,17 +1372,21 @@ static sp_status batch_impl(sp_ctx *ctx, const sp_problem *probs, int n, sp_prec
 
 extern "C" sp_status sp_project_batch(sp_ctx *ctx, int dim, const sp_problem *probs, int n, sp_precision prec, void *stream)
 {
-    if (dim != 3) return fail(SP_E_UNSUPPORTED, "batched projection supports dim 3 only");
+    if (dim != 2 && dim != 3) return fail(SP_E_INVALID_ARG, "dim must be 2 or 3");
     if (n < 0 || (n > 0 && !probs)) return fail(SP_E_INVALID_ARG, "bad problem array");
     if (n > 65535) return fail(SP_E_INVALID_ARG, "at most 65535 problems per batch");
     for (int i = 0; i < n; ++i) {
-        sp_status st = check_problem(&probs[i], 3, prec);
+        sp_status st = check_problem(&probs[i], dim, prec);
         if (st != SP_OK) return st;
     }
     if (!ctx) return fail(SP_E_INVALID_ARG, "ctx is NULL");
     if (n == 0) return SP_OK;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    return prec == SP_PREC_FP32C ? batch_impl<float>(ctx, probs, n, prec, s) : batch_impl<double>(ctx, probs, n, prec, s);
+    if (dim == 2)
+        return prec == SP_PREC_FP32C ? batch_impl<2, float>(ctx, probs, n, prec, s)
+                                     : batch_impl<2, double>(ctx, probs, n, prec, s);
+    return prec == SP_PREC_FP32C ? batch_impl<3, float>(ctx, probs, n, prec, s)
+                                 : batch_impl<3, double>(ctx, probs, n, prec, s);
 }
 
 template <int D, typename T>
@@ -1514,7 +1520,7 @@ extern "C" sp_status sp_profile_read(sp_ctx *ctx, sp_profile *out)
 // x-slabs one work item covers) and the clip blocks per CU (0 = as many as
 // fit).
 static const int kTuneSlab[] = {1, 2, 4, 8, 16};
-static const int kTuneBlocks[] = {0, 4};
+static const int kTuneBlocks[] = {0, 16};
 
 // Signature of a tuning sample: what determines the best parameters, not
 // where the buffers live.

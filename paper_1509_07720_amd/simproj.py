@@ -326,11 +326,12 @@ class Context:
         _check(st, "sp_project_tets_accurate")
         return out, total, nflag, ntag
 
-    def project_batch(self, problems, precision: str = "fp32c", stream=None) -> None:
-        """Project several 3D problems (sp_problem records built with
-        make_problem; their tensors must stay alive) in one launch."""
+    def project_batch(self, problems, precision: str = "fp32c", dim: int = 3, stream=None) -> None:
+        """Project several problems of dimension `dim` (sp_problem records
+        built with make_problem; their tensors must stay alive) in one
+        launch."""
         prec = SP_PREC_FP32C if precision == "fp32c" else SP_PREC_FP64
-        _check(sp_project_batch(self.handle, 3, list(problems), prec, _stream_ptr(stream)), "sp_project_batch")
+        _check(sp_project_batch(self.handle, dim, list(problems), prec, _stream_ptr(stream)), "sp_project_batch")
 
     def autotune(self, dim: int, sample, precision: str = "fp32c", cache_path: Optional[str] = None):
         """Tune the launch parameters on sample problems; returns
@@ -357,3 +358,26 @@ class Context:
         st, prof = sp_profile_read(self.handle)
         _check(st, "sp_profile_read")
         return {k: getattr(prof, k) for k, _ in sp_profile._fields_}
+
+
+# --------------------------------------------------------------------------
+# module-level helpers on a per-device default context
+
+_DEFAULT = {}
+
+
+def default_context(device: int = 0) -> Context:
+    """The context this module's helpers use on `device` (created once)."""
+    if device not in _DEFAULT:
+        _DEFAULT[device] = Context(device)
+    return _DEFAULT[device]
+
+
+def project(xyz, simplices, rho, dims, **kw):
+    """Context.project on the default context of the tensors' device."""
+    return default_context(xyz.device.index or 0).project(xyz, simplices, rho, dims, **kw)
+
+
+def project_batch(problems, precision: str = "fp32c", dim: int = 3, device: int = 0, stream=None) -> None:
+    """Context.project_batch on the default context of `device`."""
+    default_context(device).project_batch(problems, precision=precision, dim=dim, stream=stream)

@@ -163,8 +163,25 @@ def test_batch_rejects_bad_problem_without_launching(ctx):
     assert "dims[0]" in simproj.sp_last_error()
     torch.cuda.synchronize()
     assert float(devs[0].out.abs().sum()) == 0.0  # nothing was enqueued
-    st = simproj.sp_project_batch(ctx.handle, 2, [devs[0].rec], simproj.SP_PREC_FP32C, simproj._stream_ptr(None))
-    assert st == simproj.SP_E_UNSUPPORTED
+    st = simproj.sp_project_batch(ctx.handle, 4, [devs[0].rec], simproj.SP_PREC_FP32C, simproj._stream_ptr(None))
+    assert st == simproj.SP_E_INVALID_ARG
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_batch_2d(ctx, prec):
+    """Triangle meshes of different sizes onto different grids in one launch."""
+    probs = [synth.two_sine_2d(n=n, grid=g, seed=10 + i, per_corner=bool(i % 2))
+             for i, (n, g) in enumerate([(32, 64), (16, 48), (48, 32), (8, 128)])]
+    if prec == "fp32c":
+        probs = [synth.as_float32(p) for p in probs]
+    devs = []
+    for p in probs:
+        d = Dev(dict(p, dims=np.asarray(p["dims"])[:2]), prec)
+        devs.append(d)
+    ctx.project_batch([d.rec for d in devs], precision=prec, dim=2)
+    assert ctx.sync_status() == simproj.SP_OK, simproj.sp_last_error()
+    for i, (p, d) in enumerate(zip(probs, devs)):
+        _assert_parity(d.grid(), oracle.project(p), prec, f"2d problem {i}")
 
 
 @pytest.mark.parametrize("slab_group, blocks", [(1, 0), (2, 4), (16, 0), (4, 1)])
@@ -196,7 +213,7 @@ def test_autotune_picks_candidate_and_caches(ctx, tmp_path):
     old = ctx.tuning()
     try:
         g, c = ctx.autotune(3, [d.rec], precision=prec, cache_path=cache)
-        assert g in (1, 2, 4, 8, 16) and c in (0, 4)
+        assert g in (1, 2, 4, 8, 16) and c in (0, 16)
         lines = open(cache).read().splitlines()
         assert len(lines) == 1 and lines[0].startswith("simproj-tune 1 sig=")
         ctx.set_tuning(3, 2)
