@@ -82,7 +82,8 @@ enum {
 };
 
 /* Grid: cell (i,j,k) covers origin + [i,i+1)*h ... with h = extent/dims.
- * 2D problems use entries [0] and [1] only. */
+ * 2D problems use entries [0] and [1] only.  1 <= dims[d] <= 2^20, at most
+ * 2^35 cells in all (cell indices are 64-bit); extent[d] > 0 and finite. */
 typedef struct {
     double origin[3];
     double extent[3];

@@ -636,13 +636,15 @@ __global__ __launch_bounds__(256) void k_vd_finish(const double *acc, int64_t n_
 __global__ __launch_bounds__(256) void k_flag(const float *hi, const float *lo, const uint32_t *cmax, size_t ncell,
                                               float factor, uint8_t *flags, unsigned long long *nflag)
 {
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= ncell) return;
-    const float cm = __uint_as_float(cmax[i]);
-    const double P = (double)hi[i] + (double)lo[i];
-    const bool f = cm > 0.0f && fabs(P) < (double)cm * (double)factor;
-    flags[i] = f ? 1 : 0;
-    if (f) atomicAdd(nflag, 1ull);
+    unsigned long long nf = 0;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < ncell; i += (size_t)gridDim.x * blockDim.x) {
+        const float cm = __uint_as_float(cmax[i]);
+        const double P = (double)hi[i] + (double)lo[i];
+        const bool f = cm > 0.0f && fabs(P) < (double)cm * (double)factor;
+        flags[i] = f ? 1 : 0;
+        nf += f ? 1ull : 0ull;
+    }
+    if (nf) atomicAdd(nflag, nf);
 }
 
 // Simplices whose bounding box holds a flagged cell (boxes of more than
@@ -680,8 +682,8 @@ __global__ __launch_bounds__(256) void k_tag(ProbDev<float> p, const uint8_t *fl
 // the tagged simplices' connectivity and per-corner densities compacted.
 __global__ __launch_bounds__(256) void k_widen(const float *x, size_t n, double *y)
 {
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) y[i] = (double)x[i];
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        y[i] = (double)x[i];
 }
 
 __global__ __launch_bounds__(256) void k_gather_tagged(ProbDev<float> p, const int32_t *list, int64_t ntag,
@@ -701,12 +703,13 @@ __global__ __launch_bounds__(256) void k_gather_tagged(ProbDev<float> p, const i
 __global__ __launch_bounds__(256) void k_patch(float *hi, float *lo, const uint8_t *flags, const double *val,
                                                size_t ncell)
 {
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= ncell || !flags[i]) return;
-    const double v = val[i];
-    const float h = (float)v;
-    hi[i] = h;
-    lo[i] = (float)(v - (double)h);
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < ncell; i += (size_t)gridDim.x * blockDim.x) {
+        if (!flags[i]) continue;
+        const double v = val[i];
+        const float h = (float)v;
+        hi[i] = h;
+        lo[i] = (float)(v - (double)h);
+    }
 }
 
 // hi + lo -> out (unless the caller keeps lo), FP64 total of the grid in mass
@@ -945,7 +948,7 @@ static sp_status check_problem(const sp_problem *p, int dim, sp_precision prec)
     }
     double nc = 1.0;
     for (int d = 0; d < dim; ++d) nc *= p->grid.dims[d];
-    if (nc > 4.0e9) return fail(SP_E_INVALID_ARG, "grid of %.0f cells is too large", nc);
+    if (nc > 34359738368.0) return fail(SP_E_INVALID_ARG, "grid of %.0f cells is too large (limit 2^35)", nc);
     if (!p->out) return fail(SP_E_INVALID_ARG, "out is NULL");
     if (p->n_simplex > 0 && (!p->xyz || !p->simplices || !p->rho)) return fail(SP_E_INVALID_ARG, "xyz, simplices and rho must not be NULL");
     if (p->out_lo && prec != SP_PREC_FP32C) return fail(SP_E_INVALID_ARG, "out_lo is only used with SP_PREC_FP32C");

@@ -465,8 +465,16 @@ def as_float32(prob: Problem) -> Problem:
     kept as float64 arrays holding those float32 values), so that an FP64
     reference sees exactly the inputs an FP32 run sees."""
     p = dict(prob)
-    x32 = np.asarray(prob["xyz"], dtype=np.float32)
-    x32[x32 >= np.float32(1.0)] = np.float32(0.0)
+    x32 = np.array(prob["xyz"], dtype=np.float32)
+    # a coordinate that rounds up onto the far face of a periodic box is the
+    # same point as the near face
+    origin = np.asarray(prob.get("origin", np.zeros(3)), dtype=np.float64)
+    extent = np.asarray(prob.get("extent", np.ones(3)), dtype=np.float64)
+    periodic = prob.get("periodic", (True, True, True))
+    for d in range(x32.shape[1]):
+        if periodic[d]:
+            col = x32[:, d]
+            col[col >= np.float32(origin[d] + extent[d])] = np.float32(origin[d])
     p["xyz"] = x32.astype(np.float64)
     p["rho"] = np.asarray(prob["rho"], dtype=np.float32).astype(np.float64)
     return p

@@ -209,6 +209,25 @@ def test_non_periodic_drops_outside(ctx, prec):
     assert err["e_cell"] <= TOL[prec][0] and err["e_mass"] <= TOL[prec][1], err
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_folded_flat_simplices(ctx, prec):
+    """A stretched periodic lattice in a non-periodic box with every
+    coordinate beyond the far face folded back to 0: huge, flat and nearly
+    flat simplices (a nearly flat simplex has a huge density gradient across
+    it), parts outside the box."""
+    prob = synth.zeldovich_3d(n=16, grid=24, sigma_cells=1.0, seed=8)
+    x = np.asarray(prob["xyz"]) * 1.3 - 0.15
+    x = np.where(x.astype(np.float32) >= np.float32(1.0), 0.0, x)
+    p = dict(prob, xyz=x, periodic=(False, False, False))
+    if prec == "fp32c":
+        p = synth.as_float32(p)
+    ref = oracle.project(p)
+    assert ref["stats"]["n_zero_volume"] > 0
+    got, total = run(ctx, p, prec)
+    err = oracle.cell_error(got, ref)
+    assert err["e_cell"] <= TOL[prec][0] and err["e_mass"] <= TOL[prec][1], err
+
+
 def test_accumulate_and_out_lo(ctx):
     prob = synth.as_float32(synth.zeldovich_3d(n=16, grid=32, sigma_cells=1.5, seed=2))
     ref = oracle.project(prob)
