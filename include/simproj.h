@@ -32,7 +32,9 @@
  *                  integration in float on error-free cell-local
  *                  coordinates, per-cell compensated (hi, lo) accumulation;
  *                  double only for the orientation of near-degenerate
- *                  simplices and for the total-mass reduction.
+ *                  simplices, each simplex's density gradient (once per
+ *                  work item) and its value at one point per piece, and the
+ *                  total-mass reduction.
  *
  * Memory and streams.  Every data pointer in sp_problem is a DEVICE pointer
  * owned by the caller; the buffers must stay valid until the work enqueued
