@@ -13,6 +13,10 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
                         to cross-check the piece integrals.
 * ``mc``             -- Monte Carlo deposit, the paper's particle-sampling
                         check (Section 5.2).
+* ``vertex_density`` -- the per-vertex density estimate (Section 4).
+* ``amr``            -- the two-stage projection: exact onto grids coarsened
+                        per simplex by its smallest height, then donor cell
+                        onto the uniform grid (Section 4).
 """
 from __future__ import annotations
 
