@@ -148,6 +148,26 @@ sp_status sp_project_tris(sp_ctx *ctx, const sp_problem *prob, sp_precision prec
 sp_status sp_project_tets_accurate(sp_ctx *ctx, const sp_problem *prob, int accurate_bits, int wrong_bits,
                                    int64_t *counts, void *stream);
 
+/* Two-stage projection of tetrahedra onto a coarsened-then-gathered grid
+ * (Section 4, "Calculation of the acceleration": exact projection onto an
+ * adaptive grid whose cells are no larger than the smallest simplex height
+ * they meet, then donor cell onto the uniform grid).  Read per simplex here:
+ * a tetrahedron whose smallest height (3 V / largest face area, in cells of
+ * this grid, after the minimum-image unwrap, in FP64) is h is projected
+ * exactly onto the grid coarsened 2^l times per axis, l = floor(log2 h)
+ * clamped to [0, max_level]; every coarse cell's mass is then spread evenly
+ * over the 8^l cells it covers and the levels are summed.  Large simplices
+ * thus cost pieces at their own resolution; the result is the exact
+ * projection only where every simplex has level 0 (max_level 0 is
+ * sp_project_tets).
+ *   prob          as for sp_project_tets (SP_ACCUMULATE rejected)
+ *   max_level     0..10; every dims[d] must be a multiple of 2^max_level
+ *   level_counts  optional HOST int64[max_level + 1]: simplices per level
+ * Synchronises with `stream` once (to size the levels); the levels are
+ * projected in one batched launch (sp_project_batch). */
+sp_status sp_project_tets_amr(sp_ctx *ctx, const sp_problem *prob, sp_precision prec, int max_level,
+                              int64_t *level_counts, void *stream);
+
 /* Project n independent problems of dimension `dim` (2 or 3; 1 <= n <=
  * 65535, n == 0 is a no-op) in one persistent, work-stealing
  * launch; `probs` is a HOST array of n problems whose buffers are device

@@ -712,6 +712,86 @@ __global__ __launch_bounds__(256) void k_patch(float *hi, float *lo, const uint8
     }
 }
 
+// Two-stage projection (Section 4, "Calculation of the acceleration"): each
+// tetrahedron is projected exactly onto the grid coarsened 2^l times per
+// axis, l = floor(log2 h) clamped to [0, max_level], h its smallest height
+// (3 V / largest face area) in fine-cell units after the minimum-image
+// unwrap, all in FP64; the coarse grids are then spread onto the fine grid
+// by donor cell.
+template <typename T>
+__global__ __launch_bounds__(256) void k_amr_level(ProbDev<T> p, int max_level, uint8_t *level, unsigned *counts)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= p.n) return;
+    int lv = 0;
+    int32_t vi[4];
+    bool ok = true;
+    for (int a = 0; a < 4; ++a) {
+        vi[a] = p.simp[s * 4 + a];
+        ok = ok && vi[a] >= 0 && vi[a] < p.n_vert;
+    }
+    if (ok) {
+        double e[3][3];
+        for (int a = 1; a < 4; ++a) {
+            for (int d = 0; d < 3; ++d) {
+                double dx = (double)p.xyz[(int64_t)vi[a] * 3 + d] - (double)p.xyz[(int64_t)vi[0] * 3 + d];
+                if (p.g.periodic[d]) dx -= p.g.extent[d] * rint(dx / p.g.extent[d]);
+                e[a - 1][d] = dx * p.g.scale[d];
+            }
+        }
+        auto cross = [](const double *x, const double *y, double *z) {
+            z[0] = x[1] * y[2] - x[2] * y[1];
+            z[1] = x[2] * y[0] - x[0] * y[2];
+            z[2] = x[0] * y[1] - x[1] * y[0];
+        };
+        auto norm = [](const double *z) { return sqrt(z[0] * z[0] + z[1] * z[1] + z[2] * z[2]); };
+        double c01[3], c02[3], c12[3], f[3], g[3], c3[3];
+        cross(e[0], e[1], c01);
+        cross(e[0], e[2], c02);
+        cross(e[1], e[2], c12);
+        for (int d = 0; d < 3; ++d) {
+            f[d] = e[1][d] - e[0][d];
+            g[d] = e[2][d] - e[0][d];
+        }
+        cross(f, g, c3);
+        const double V = fabs(e[0][0] * c12[0] + e[0][1] * c12[1] + e[0][2] * c12[2]) / 6.0;
+        const double amax = fmax(fmax(norm(c01), norm(c02)), fmax(norm(c12), norm(c3))) / 2.0;
+        const double h = amax > 0.0 ? 3.0 * V / amax : 0.0;
+        if (h >= 1.0 && isfinite(h)) {
+            lv = (int)floor(log2(h));
+            lv = lv > max_level ? max_level : lv;
+        }
+    }
+    level[s] = (uint8_t)lv;
+    atomicAdd(&counts[lv], 1u);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_amr_scatter(ProbDev<T> p, const uint8_t *level, unsigned *cursor,
+                                                     const unsigned *base, int32_t *simp, T *rho)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= p.n) return;
+    const int lv = level[s];
+    const int64_t t = (int64_t)base[lv] + atomicAdd(&cursor[lv], 1u);
+    for (int a = 0; a < 4; ++a) {
+        simp[t * 4 + a] = p.simp[s * 4 + a];
+        if (rho) rho[t * 4 + a] = p.rho[s * 4 + a];
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_donor(T *out, const T *coarse, int lv, int nx, int ny, size_t ncell, T factor)
+{
+    const int cnx = nx >> lv, cny = ny >> lv;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < ncell; i += (size_t)gridDim.x * blockDim.x) {
+        const size_t x = i % (size_t)nx, yz = i / (size_t)nx;
+        const size_t y = yz % (size_t)ny, z = yz / (size_t)ny;
+        const size_t c = ((z >> lv) * (size_t)cny + (y >> lv)) * (size_t)cnx + (x >> lv);
+        out[i] += coarse[c] * factor;
+    }
+}
+
 // hi + lo -> out (unless the caller keeps lo), FP64 total of the grid in mass
 // units.
 template <typename T>
@@ -1004,7 +1084,8 @@ struct Prepared {
 
 // Scratch layout and descriptors for a launch over n problems.
 template <int D, typename T>
-static sp_status prepare(sp_ctx *ctx, const sp_problem *probs, int n, std::vector<Prepared<T>> &out, int64_t &ntotal)
+static sp_status prepare(sp_ctx *ctx, const sp_problem *probs, int n, std::vector<Prepared<T>> &out, int64_t &ntotal,
+                         bool batched = false)
 {
     const bool fp32 = sizeof(T) == 4;
     ntotal = 0;
@@ -1024,7 +1105,7 @@ static sp_status prepare(sp_ctx *ctx, const sp_problem *probs, int n, std::vecto
     const size_t o_items = off;
     off = align_up(off + sizeof(uint64_t) * nitems);
     const size_t o_iprob = off;
-    if (n > 1) off = align_up(off + sizeof(uint16_t) * nitems);
+    if (batched) off = align_up(off + sizeof(uint16_t) * nitems);  // problem id per item
     const size_t o_ovf = off;
     off = align_up(off + sizeof(Ovf) * OVF_CAP);
     const size_t o_lo = off;
@@ -1068,7 +1149,7 @@ static sp_status prepare(sp_ctx *ctx, const sp_problem *probs, int n, std::vecto
         p.tinfo = reinterpret_cast<uint32_t *>(base + o_tinfo) + toff;
         toff += prob->n_simplex;
         p.items = reinterpret_cast<uint64_t *>(base + o_items);
-        p.item_prob = n > 1 ? reinterpret_cast<uint16_t *>(base + o_iprob) : nullptr;
+        p.item_prob = batched ? reinterpret_cast<uint16_t *>(base + o_iprob) : nullptr;
         p.extra_cap = extra_cap;
         p.ovf = reinterpret_cast<Ovf *>(base + o_ovf);
         p.cs = ctx->cs;
@@ -1294,6 +1375,112 @@ extern "C" sp_status sp_project_tets_accurate(sp_ctx *ctx, const sp_problem *pro
     return SP_OK;
 }
 
+template <int D, typename T>
+static sp_status batch_impl(sp_ctx *ctx, const sp_problem *probs, int n, sp_precision prec, hipStream_t stream);
+
+template <typename T>
+static sp_status amr_impl(sp_ctx *ctx, const sp_problem *prob, sp_precision prec, int max_level, int64_t *level_counts,
+                          hipStream_t s)
+{
+    HIPCHECK(hipSetDevice(ctx->device));
+    const int64_t n = prob->n_simplex;
+    const bool per_corner = (prob->grid.flags & SP_RHO_PER_CORNER) != 0;
+    size_t ncell = 1;
+    for (int d = 0; d < 3; ++d) ncell *= (size_t)prob->grid.dims[d];
+    // buffers: levels, counters, bases, compacted simplices (and corner
+    // densities), one coarse grid per level >= 1
+    size_t off = 0;
+    const size_t o_lv = off;
+    off = align_up(off + (size_t)(n > 0 ? n : 1));
+    const size_t o_cnt = off;
+    off = align_up(off + 3 * 16 * sizeof(unsigned));
+    const size_t o_simp = off;
+    off = align_up(off + sizeof(int32_t) * 4 * (size_t)(n > 0 ? n : 1));
+    const size_t o_rho = off;
+    off = align_up(off + (per_corner ? sizeof(T) * 4 * (size_t)n : 0));
+    size_t o_coarse[16] = {0};
+    for (int l = 1; l <= max_level; ++l) {
+        o_coarse[l] = off;
+        off = align_up(off + sizeof(T) * (ncell >> (3 * l)));
+    }
+    sp_status st = ensure_buf(ctx->aux[1], off);
+    if (st != SP_OK) return st;
+    char *base = static_cast<char *>(ctx->aux[1].p);
+    uint8_t *lv = reinterpret_cast<uint8_t *>(base + o_lv);
+    unsigned *counts = reinterpret_cast<unsigned *>(base + o_cnt);
+    unsigned *cursor = counts + 16;
+    unsigned *bases = counts + 32;
+    int32_t *simp = reinterpret_cast<int32_t *>(base + o_simp);
+    T *rho = per_corner ? reinterpret_cast<T *>(base + o_rho) : nullptr;
+    std::vector<Prepared<T>> v;
+    int64_t ntot = 0;
+    // a descriptor of the input, for the per-simplex kernels
+    st = prepare<3, T>(ctx, prob, 1, v, ntot);
+    if (st != SP_OK) return st;
+    const ProbDev<T> pin = v[0].p;
+    unsigned hc[16] = {0}, hb[16] = {0};
+    hipLaunchKernelGGL(k_fill<unsigned>, dim3(1), dim3(64), 0, s, counts, (size_t)48);
+    if (n > 0) {
+        hipLaunchKernelGGL(k_amr_level<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, pin, max_level, lv, counts);
+        HIPCHECK(hipMemcpyAsync(hc, counts, sizeof hc, hipMemcpyDeviceToHost, s));
+        HIPCHECK(hipStreamSynchronize(s));
+        for (int l = 1; l <= max_level; ++l) hb[l] = hb[l - 1] + hc[l - 1];
+        HIPCHECK(hipMemcpyAsync(bases, hb, sizeof hb, hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_amr_scatter<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, pin,
+                           (const uint8_t *)lv, cursor, (const unsigned *)bases, simp, rho);
+        HIPCHECK(hipStreamSynchronize(s));  // bases[] is read from host memory above
+    }
+    // one problem per level (level 0 writes the caller's grid), projected in
+    // one batched launch; all levels add to the caller's total
+    std::vector<sp_problem> probs;
+    std::vector<int> plev;
+    for (int l = 0; l <= max_level; ++l) {
+        if (l > 0 && hc[l] == 0) continue;
+        sp_problem q = *prob;
+        q.simplices = simp + 4 * (size_t)hb[l];
+        q.n_simplex = hc[l];
+        if (per_corner) q.rho = rho + 4 * (size_t)hb[l];
+        for (int d = 0; d < 3; ++d) q.grid.dims[d] = prob->grid.dims[d] >> l;
+        if (l > 0) {
+            q.out = base + o_coarse[l];
+            q.out_lo = nullptr;
+        }
+        probs.push_back(q);
+        plev.push_back(l);
+    }
+    st = batch_impl<3, T>(ctx, probs.data(), (int)probs.size(), prec, s);
+    if (st != SP_OK) return st;
+    const bool mass = (prob->grid.flags & SP_OUT_MASS) != 0;
+    for (size_t k = 0; k < probs.size(); ++k) {
+        const int l = plev[k];
+        if (l == 0) continue;
+        const T factor = mass ? (T)(1.0 / (double)(1ull << (3 * l))) : T(1);
+        hipLaunchKernelGGL(k_donor<T>, dim3(grid_blocks(ncell, 256)), dim3(256), 0, s, (T *)prob->out,
+                           (const T *)probs[k].out, l, prob->grid.dims[0], prob->grid.dims[1], ncell, factor);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(SP_E_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+    if (level_counts)
+        for (int l = 0; l <= max_level; ++l) level_counts[l] = hc[l];
+    return SP_OK;
+}
+
+extern "C" sp_status sp_project_tets_amr(sp_ctx *ctx, const sp_problem *prob, sp_precision prec, int max_level,
+                                         int64_t *level_counts, void *stream)
+{
+    sp_status st = check_problem(prob, 3, prec);
+    if (st != SP_OK) return st;
+    if (prob->grid.flags & SP_ACCUMULATE) return fail(SP_E_INVALID_ARG, "SP_ACCUMULATE is not supported here");
+    if (max_level < 0 || max_level > 10) return fail(SP_E_INVALID_ARG, "max_level %d not in 0..10", max_level);
+    for (int d = 0; d < 3; ++d)
+        if (prob->grid.dims[d] % (1 << max_level) != 0)
+            return fail(SP_E_INVALID_ARG, "dims[%d] = %d is not a multiple of 2^max_level", d, prob->grid.dims[d]);
+    if (!ctx) return fail(SP_E_INVALID_ARG, "ctx is NULL");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    return prec == SP_PREC_FP32C ? amr_impl<float>(ctx, prob, prec, max_level, level_counts, s)
+                                 : amr_impl<double>(ctx, prob, prec, max_level, level_counts, s);
+}
+
 // FNV-1a over the bytes that determine a batched launch.
 static uint64_t fnv(uint64_t h, const void *data, size_t n)
 {
@@ -1311,7 +1498,7 @@ static sp_status batch_impl(sp_ctx *ctx, const sp_problem *probs, int n, sp_prec
     HIPCHECK(hipSetDevice(ctx->device));
     std::vector<Prepared<T>> v;
     int64_t ntotal = 0;
-    sp_status st = prepare<D, T>(ctx, probs, n, v, ntotal);
+    sp_status st = prepare<D, T>(ctx, probs, n, v, ntotal, true);
     if (st != SP_OK) return st;
     uint64_t key = 1469598103934665603ull;
     const int dim = D;

@@ -76,6 +76,9 @@ for _name in ("sp_project_tets", "sp_project_tris"):
 _lib.sp_project_tets_accurate.argtypes = [_V, ctypes.POINTER(sp_problem), ctypes.c_int, ctypes.c_int,
                                           ctypes.POINTER(ctypes.c_int64), _V]
 _lib.sp_project_tets_accurate.restype = ctypes.c_int
+_lib.sp_project_tets_amr.argtypes = [_V, ctypes.POINTER(sp_problem), ctypes.c_int, ctypes.c_int,
+                                     ctypes.POINTER(ctypes.c_int64), _V]
+_lib.sp_project_tets_amr.restype = ctypes.c_int
 _lib.sp_project_batch.argtypes = [_V, ctypes.c_int, ctypes.POINTER(sp_problem), ctypes.c_int, ctypes.c_int, _V]
 _lib.sp_project_batch.restype = ctypes.c_int
 _lib.sp_sync_status.argtypes = [_V, _V]
@@ -136,6 +139,12 @@ def sp_project_tets_accurate(ctx, prob: sp_problem, accurate_bits: int, wrong_bi
     counts = (ctypes.c_int64 * 2)()
     st = _lib.sp_project_tets_accurate(ctx, ctypes.byref(prob), int(accurate_bits), int(wrong_bits), counts, stream)
     return st, counts[0], counts[1]
+
+
+def sp_project_tets_amr(ctx, prob: sp_problem, prec: int, max_level: int, stream=None):
+    counts = (ctypes.c_int64 * (max(0, int(max_level)) + 1))()
+    st = _lib.sp_project_tets_amr(ctx, ctypes.byref(prob), int(prec), int(max_level), counts, stream)
+    return st, list(counts)
 
 
 def sp_project_batch(ctx, dim: int, probs: Sequence[sp_problem], prec: int, stream=None) -> int:
@@ -325,6 +334,28 @@ class Context:
         st, nflag, ntag = sp_project_tets_accurate(self.handle, p, accurate_bits, wrong_bits, _stream_ptr(stream))
         _check(st, "sp_project_tets_accurate")
         return out, total, nflag, ntag
+
+    def project_amr(self, xyz, simplices, rho, dims, max_level: int, origin=(0.0, 0.0, 0.0),
+                    extent=(1.0, 1.0, 1.0), periodic=(True, True, True), precision: str = "fp32c",
+                    rho_per_corner: bool = False, out=None, out_mass: bool = False, validate: bool = False,
+                    want_total: bool = True, stream=None):
+        """Two-stage projection (sp_project_tets_amr); returns (grid,
+        total_mass, simplices per level)."""
+        import torch
+
+        prec = SP_PREC_FP32C if precision == "fp32c" else SP_PREC_FP64
+        dt = torch.float32 if prec == SP_PREC_FP32C else torch.float64
+        if xyz.dtype != dt or rho.dtype != dt or simplices.dtype != torch.int32:
+            raise TypeError(f"xyz and rho must be {dt}, simplices int32")
+        shape = tuple(int(d) for d in reversed(list(dims)[:3]))
+        if out is None:
+            out = torch.empty(shape, dtype=dt, device=xyz.device)
+        total = torch.zeros(1, dtype=torch.float64, device=xyz.device) if want_total else None
+        p = make_problem(xyz, simplices, rho, dims, origin, extent, periodic, rho_per_corner, out, None, total,
+                         out_mass, False, validate)
+        st, counts = sp_project_tets_amr(self.handle, p, prec, max_level, _stream_ptr(stream))
+        _check(st, "sp_project_tets_amr")
+        return out, total, counts
 
     def project_batch(self, problems, precision: str = "fp32c", dim: int = 3, stream=None) -> None:
         """Project several problems of dimension `dim` (sp_problem records

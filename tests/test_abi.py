@@ -22,7 +22,7 @@ def test_header_declares_the_boundary():
     names = _declared()
     for n in ("sp_create", "sp_destroy", "sp_project_tets", "sp_project_tris", "sp_project_batch",
               "sp_sync_status", "sp_autotune", "sp_last_error", "sp_vertex_density", "sp_tuning_set",
-              "sp_tuning_read", "sp_project_tets_accurate"):
+              "sp_tuning_read", "sp_project_tets_accurate", "sp_project_tets_amr"):
         assert n in names
 
 
@@ -165,3 +165,15 @@ def test_accurate_host_validation():
     p.grid.flags |= simproj.SP_ACCUMULATE
     st, _, _ = simproj.sp_project_tets_accurate(None, p, 10, 10)
     assert st == simproj.SP_E_INVALID_ARG and "SP_ACCUMULATE" in simproj.sp_last_error()
+
+
+def test_amr_host_validation():
+    from paper_1509_07720_amd import simproj
+
+    p = _prob()
+    st, _ = simproj.sp_project_tets_amr(None, p, simproj.SP_PREC_FP32C, 2)
+    assert st == simproj.SP_E_INVALID_ARG and "ctx is NULL" in simproj.sp_last_error()
+    st, _ = simproj.sp_project_tets_amr(None, p, simproj.SP_PREC_FP32C, 11)
+    assert st == simproj.SP_E_INVALID_ARG and "max_level" in simproj.sp_last_error()
+    st, _ = simproj.sp_project_tets_amr(None, p, simproj.SP_PREC_FP32C, 4)  # dims 8 not a multiple of 16
+    assert st == simproj.SP_E_INVALID_ARG and "multiple" in simproj.sp_last_error()

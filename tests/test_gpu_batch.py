@@ -152,6 +152,19 @@ def test_batch_per_problem_flags(ctx):
     assert float(c.total.cpu()[0]) == 0.0
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_batch_of_one_problem(ctx, prec):
+    """A batch may hold a single problem (its items still carry a problem
+    id)."""
+    p = small_batch(count=1, seed_base=4400)[0]
+    if prec == "fp32c":
+        p = synth.as_float32(p)
+    d = Dev(p, prec)
+    ctx.project_batch([d.rec], precision=prec)
+    assert ctx.sync_status() == simproj.SP_OK, simproj.sp_last_error()
+    _assert_parity(d.grid(), _ref(p, prec), prec, "single-problem batch")
+
+
 def test_batch_rejects_bad_problem_without_launching(ctx):
     prec = "fp32c"
     probs = [synth.as_float32(p) for p in small_batch(count=2, seed_base=4300)]
