@@ -10,8 +10,9 @@ with the FP64 total-mass reduction.  Inputs are resident in HBM before the
 timed region.  The same workload is also timed in FP64 mode.
 
 Also reported (not part of `value`): the per-vertex density estimate on the
-64^3 lattice, and the accuracy-controlled projection of cancelling densities
-against plain FP32C and FP64.  With --batch, the batched workload (64
+64^3 lattice, the accuracy-controlled projection of cancelling densities
+against plain FP32C and FP64, and the two-stage (coarsened + donor-cell)
+projection against the exact one.  With --batch, the batched workload (64
 Zel'dovich meshes of 1e4..2e6 tets onto grids of 32^3..256^3) is also timed:
 one captured graph launch for all 64 problems against 64 sequential calls,
 in FP32C and FP64.
@@ -236,6 +237,47 @@ def accuracy_leg(ctx, steps, warmup):
     return res
 
 
+def amr_leg(ctx, steps, warmup):
+    """Two-stage projection against the exact one where simplices are large
+    against the cells: the 32^3 Zel'dovich lattice (196,608 tets of ~8 cells)
+    onto 256^3, FP32C, max_level 3.  Reports both times, the simplices per
+    level and the L1 difference of the two grids relative to the total."""
+    import torch
+
+    from paper_1509_07720_amd import synth
+
+    prob = synth.zeldovich_3d(n=32, grid=256, sigma_cells=1.5, seed=44)
+    dev = torch.device("cuda:0")
+    x = torch.tensor(prob["xyz"], dtype=torch.float32, device=dev)
+    s = torch.tensor(prob["simplices"], dtype=torch.int32, device=dev)
+    r = torch.tensor(prob["rho"], dtype=torch.float32, device=dev)
+    dims = [256] * 3
+    res = {"workload": "zeldovich-32^3-lattice-to-256^3", "n_simplex": int(s.shape[0]), "max_level": 3}
+    outs = {}
+    for name in ("exact", "amr"):
+        def fn():
+            if name == "exact":
+                return ctx.project(x, s, r, dims, precision="fp32c", out_mass=True)[0], None
+            g, _, counts = ctx.project_amr(x, s, r, dims, 3, precision="fp32c", out_mass=True)
+            return g, counts
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            g, counts = fn()
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / steps
+        outs[name] = g
+        res[name] = {"ms": sec * 1e3, "simplices_per_s": s.shape[0] / sec}
+        if counts is not None:
+            res[name]["simplices_per_level"] = counts
+        log(f"amr leg {name}: {sec * 1e3:.2f} ms")
+    res["l1_difference_rel"] = float((outs["amr"].double() - outs["exact"].double()).abs().sum() /
+                                     outs["exact"].double().abs().sum())
+    return res
+
+
 def time_steps(ctx, args_dev, steps, warmup, prec):
     import torch
 
@@ -269,6 +311,7 @@ def main() -> int:
     ap.add_argument("--no-atomic-peak", action="store_true", help="skip the atomic-rate measurement (mbench)")
     ap.add_argument("--no-vertex-density", action="store_true", help="skip the per-vertex density leg")
     ap.add_argument("--no-accuracy", action="store_true", help="skip the accuracy-control leg")
+    ap.add_argument("--no-amr", action="store_true", help="skip the two-stage projection leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (--gpus must be 1)", file=sys.stderr)
@@ -336,6 +379,7 @@ def main() -> int:
     batch = batch_leg(ctx, max(1, min(args.steps, 3)), 1) if args.batch else None
     vdens = None if args.no_vertex_density else vertex_density_leg(ctx, max(1, args.steps), 1)
     accur = None if args.no_accuracy else accuracy_leg(ctx, max(1, min(args.steps, 5)), 1)
+    amr = None if args.no_amr else amr_leg(ctx, max(1, min(args.steps, 5)), 1)
 
     traffic, traffic_src = clip_traffic()
     deposits_per_s = pieces / (clip_ms * 1e-3)
@@ -388,6 +432,7 @@ def main() -> int:
         "batch": batch,
         "vertex_density": vdens,
         "accuracy_control": accur,
+        "two_stage": amr,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
