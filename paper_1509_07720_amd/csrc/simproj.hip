@@ -36,7 +36,13 @@ namespace {
 
 constexpr int WG = 64;       // lanes per block in the clip kernels (one wave)
 constexpr int NCLS = 16;     // cost classes
-constexpr int MAXV3 = 18;    // polytope vertex slots per lane (no overflow measured at 18)
+// Polytope vertex slots per lane.  FP32: 17 slots (17 KB of LDS per wave)
+// let 9 waves share a CU when the kernel keeps to 168 VGPRs (3 waves per
+// SIMD); the rare polytope that needs more is finished by the 32-slot
+// kernel.  FP64 (32-byte slots) is bound to 4-5 waves by its LDS either
+// way and keeps 18 slots, which it never overflowed in the tests.
+template <typename T>
+constexpr int maxv3() { return sizeof(T) == 4 ? 17 : 18; }
 constexpr int MAXV3_BIG = 32;
 constexpr int MAXP2 = 12;    // polygon vertices per lane and buffer (peak 8)
 constexpr int OVF_CAP = 1 << 16;
@@ -440,8 +446,9 @@ __global__ __launch_bounds__(256) void k_scatter(ProbDev<T> p0, Batch b)
 // the queue state is wave-uniform (ballots, no LDS and no barriers) and the
 // only LDS is each lane's own polytope.  Per loop iteration a busy lane
 // performs one sweep step (a column build if due, then one piece).
-template <int D, typename T, int MAXV>
-__global__ __launch_bounds__(WG) void k_clip(ProbDev<T> p0, Batch b, int overflow_pass)
+template <int D, typename T, int MAXV, bool SINGLE>
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1))) void k_clip(
+    ProbDev<T> p0, Batch b, int overflow_pass)
 {
     static_assert(WG == 64, "the queue logic assumes one wave per block");
     const ProbDev<T> &p = p0;  // fields shared by every problem of the launch
@@ -450,6 +457,8 @@ __global__ __launch_bounds__(WG) void k_clip(ProbDev<T> p0, Batch b, int overflo
     const int lane = threadIdx.x;
     const unsigned total = overflow_pass ? min(p.cs->ovf_count, (unsigned)OVF_CAP) : p.cs->total;
     unsigned *head = overflow_pass ? &p.cs->ovf_head : &p.cs->head;
+    // the few resumed items of the overflow pass are spread over many waves
+    const unsigned chunk = overflow_pass ? 8u : (unsigned)WG;
     unsigned q_base = 0u, q_n = 0u, q_h = 0u;  // current chunk [q_base, q_base + q_n), next unclaimed q_h
     bool q_done = false;
     Poly3<T, MAXV, WG> P3;
@@ -469,13 +478,13 @@ __global__ __launch_bounds__(WG) void k_clip(ProbDev<T> p0, Batch b, int overflo
         const uint64_t idle = __ballot(!busy);
         if (idle != 0ull && q_h >= q_n && !q_done) {
             unsigned base = 0u;
-            if (lane == 0) base = atomicAdd(head, (unsigned)WG);
+            if (lane == 0) base = atomicAdd(head, chunk);
             base = __builtin_amdgcn_readfirstlane(base);
             if (base >= total) {
                 q_done = true;
             } else {
                 q_base = base;
-                q_n = min((unsigned)WG, total - base);
+                q_n = min(chunk, total - base);
                 q_h = 0u;
             }
         }
@@ -500,9 +509,9 @@ __global__ __launch_bounds__(WG) void k_clip(ProbDev<T> p0, Batch b, int overflo
                     sid = (int64_t)(uint32_t)item;
                     sb = (int)((item >> 32) & 0xffffu);
                     sc = (int)(item >> 48);
-                    pid = b.nprob ? (int)p.item_prob[it] : 0;
+                    pid = !SINGLE && b.nprob ? (int)p.item_prob[it] : 0;
                 }
-                const ProbDev<T> q = b.nprob ? static_cast<const ProbDev<T> *>(b.probs)[pid] : p0;
+                const ProbDev<T> q = !SINGLE && b.nprob ? static_cast<const ProbDev<T> *>(b.probs)[pid] : p0;
                 Local<T> L0;
                 if (setup_any<D>(q, sid, false, L0) == SETUP_OK) {
                     const SweepOrder ord = D == 3 ? sweep_order(L0) : kIdentity;
@@ -1196,23 +1205,28 @@ static void enqueue(sp_ctx *ctx, const std::vector<Prepared<T>> &v, const Batch 
             if (single) hipLaunchKernelGGL((k_scatter<T, false>), dim3(nb), dim3(256), 0, stream, p0, b);
             else hipLaunchKernelGGL((k_scatter<T, true>), dim3(nb), dim3(256), 0, stream, p0, b);
         }
+        constexpr int MAXV3 = maxv3<T>();
+        // a single FP32 problem takes the instance whose problem fields are
+        // kernel arguments (uniform registers); the FP64 kernel measured
+        // faster with the run-time choice for both forms
+        const bool one = fp32 && single;
+        auto kclip = one ? k_clip<D, T, MAXV3, true> : k_clip<D, T, MAXV3, false>;
+        auto kretry = D == 3 ? (one ? k_clip<D, T, MAXV3_BIG, true> : k_clip<D, T, MAXV3_BIG, false>) : kclip;
         int occ = 0;
-        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_clip<D, T, MAXV3>, WG, 0);
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kclip, WG, 0);
         if (occ < 1) occ = 1;
         const int cpc = ctx->tune.chunks_per_cu > 0 ? ctx->tune.chunks_per_cu : occ;
         const int blocks = ctx->num_cu * cpc;
         ctx->last_clip_blocks = blocks;
         {
             StageTimer t = timer(ST_CLIP);
-            hipLaunchKernelGGL((k_clip<D, T, MAXV3>), dim3(blocks), dim3(WG), 0, stream, p0, b, 0);
+            hipLaunchKernelGGL(kclip, dim3(blocks), dim3(WG), 0, stream, p0, b, 0);
         }
         {
             StageTimer t = timer(ST_RETRY);
-            if (D == 3) {
-                hipLaunchKernelGGL((k_clip<D, T, MAXV3_BIG>), dim3(ctx->num_cu), dim3(WG), 0, stream, p0, b, 1);
-            } else {
-                hipLaunchKernelGGL((k_clip<D, T, MAXV3>), dim3(ctx->num_cu), dim3(WG), 0, stream, p0, b, 1);
-            }
+            int rocc = 0;
+            (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&rocc, kretry, WG, 0);
+            hipLaunchKernelGGL(kretry, dim3(ctx->num_cu * (rocc < 1 ? 1 : rocc)), dim3(WG), 0, stream, p0, b, 1);
         }
     }
     {
