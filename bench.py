@@ -44,6 +44,7 @@ MBENCH = os.path.join(ROOT, "paper_1509_07720_amd", "mbench")
 # density sum).  See the design notes for the derivation.
 FLOPS_PER_PIECE = 60 + 12 + 240
 PEAK_FP32_TFLOPS = 157.3
+PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 
 
@@ -86,9 +87,10 @@ def clip_traffic():
     return rec["fetch_kib"] * 1024.0 * f_scale + rec["write_kib"] * 1024.0 * w_scale, "counters"
 
 
-def atomic_peak():
-    """Measured rate of compensated FP32 atomic adds to random cells of a
-    256^3 grid (the deposit's pattern), from the mbench program."""
+def atomic_peaks():
+    """Measured rates of atomic adds to random cells of a 64 MiB grid (the
+    deposit's pattern), from the mbench program: {"fp32c": compensated FP32
+    pairs/s, "fp64": FP64 adds/s}, or None."""
     import subprocess
 
     if not os.path.exists(MBENCH):
@@ -97,9 +99,12 @@ def atomic_peak():
         out = subprocess.run([MBENCH, "atomic", "64", "3"], capture_output=True, text=True, timeout=120)
     except (OSError, subprocess.TimeoutExpired):
         return None
-    rates = [json.loads(l)["adds_per_s"] for l in out.stdout.splitlines()
-             if l.startswith("{") and "returning+compensated" in l]
-    return max(rates) if rates else None
+    recs = [json.loads(l) for l in out.stdout.splitlines() if l.startswith("{")]
+    peak = {}
+    for prec, kind in (("fp32c", "returning+compensated"), ("fp64", "f64")):
+        rates = [r["adds_per_s"] for r in recs if r.get("kind") == kind]
+        peak[prec] = max(rates) if rates else None
+    return peak
 
 
 def batch_leg(ctx, steps, warmup):
@@ -278,6 +283,78 @@ def amr_leg(ctx, steps, warmup):
     return res
 
 
+def configs_leg(ctx, steps, warmup, peaks, refined=True):
+    """The other 3D configurations, each in FP32C and FP64: the 64^3
+    Zel'dovich lattice onto 128^3 (1.57M tets, per-vertex densities) and the
+    two-level refined 128^3 lattice onto 512^3 (50.3M tets, heavy shell
+    crossing).  Per precision: time per call, pieces, error of the total mass,
+    and the three fractions -- ALU (pieces x FLOPS_PER_PIECE over the clip
+    kernel's time against the vector peak of that precision), HBM (inputs read
+    once plus the output grids written once, over the call) and atomic
+    (deposits over the clip kernel's time against the measured rate)."""
+    import torch
+
+    from paper_1509_07720_amd import synth
+
+    work = [("zeldovich-64^3-lattice-to-128^3", lambda: synth.zeldovich_3d(n=64, grid=128, sigma_cells=1.5, seed=2))]
+    if refined:
+        work.append(("refined-128^3-kuhn-2-levels-to-512^3",
+                     lambda: synth.refined_3d(n=128, grid=512, sigma_cells=4.0, seed=5)))
+    dev = torch.device("cuda:0")
+    res = {}
+    for name, gen in work:
+        t = time.time()
+        prob = synth.as_float32(gen())
+        exact = exact_total(prob)
+        log(f"config {name}: generated in {time.time() - t:.1f}s")
+        dims = [int(d) for d in prob["dims"]]
+        per_corner = bool(prob["rho_per_corner"])
+        simp = torch.from_numpy(np.ascontiguousarray(prob["simplices"], dtype=np.int32)).to(dev)
+        row = {"n_simplex": int(simp.shape[0]), "grid": dims, "rho": "per-corner" if per_corner else "per-vertex"}
+        for prec, dt, nb, peak_alu in (("fp32c", torch.float32, 4, PEAK_FP32_TFLOPS),
+                                       ("fp64", torch.float64, 8, PEAK_FP64_TFLOPS)):
+            xyz = torch.from_numpy(np.asarray(prob["xyz"])).to(dev, dt).contiguous()
+            rho = torch.from_numpy(np.asarray(prob["rho"])).to(dev, dt).contiguous()
+            out = torch.empty(tuple(reversed(dims)), dtype=dt, device=dev)
+
+            def call():
+                return ctx.project(xyz, simp, rho, dims, precision=prec, rho_per_corner=per_corner, out=out,
+                                   out_mass=True)
+
+            ctx.profile(2)
+            call()
+            pieces = ctx.profile_read()["pieces"]
+            ctx.profile(0)
+            for _ in range(warmup):
+                call()
+            torch.cuda.synchronize()
+            ctx.profile(1)
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                call()
+            torch.cuda.synchronize()
+            sec = (time.perf_counter() - t0) / steps
+            prof = ctx.profile_read()
+            ctx.profile(0)
+            _, total = call()
+            assert ctx.sync_status() == 0
+            clip_s = prof["ms_clip"] / max(prof["calls"], 1) * 1e-3
+            algo = xyz.numel() * nb + simp.numel() * 4 + rho.numel() * nb + out.numel() * (8 if prec == "fp32c" else nb)
+            dep_rate = pieces / clip_s
+            apk = peaks.get(prec) if peaks else None
+            row[prec] = {"ms_per_call": sec * 1e3, "simplices_per_s": simp.shape[0] / sec, "clip_ms": clip_s * 1e3,
+                         "pieces": pieces, "mass_rel_err": abs(float(total.cpu()[0]) - exact) / exact,
+                         "alu_frac": pieces * FLOPS_PER_PIECE / clip_s / 1e12 / peak_alu,
+                         "hbm_frac": algo / sec / 1e9 / PEAK_HBM_GBS,
+                         "atomic_frac": dep_rate / apk if apk else None, "deposits_per_s": dep_rate}
+            log(f"config {name} {prec}: {sec * 1e3:.2f} ms/call, {pieces} pieces")
+            del xyz, rho, out
+        res[name] = row
+        del simp, prob
+        torch.cuda.empty_cache()
+    return res
+
+
 def time_steps(ctx, args_dev, steps, warmup, prec):
     import torch
 
@@ -312,13 +389,16 @@ def main() -> int:
     ap.add_argument("--no-vertex-density", action="store_true", help="skip the per-vertex density leg")
     ap.add_argument("--no-accuracy", action="store_true", help="skip the accuracy-control leg")
     ap.add_argument("--no-amr", action="store_true", help="skip the two-stage projection leg")
+    ap.add_argument("--no-configs", action="store_true", help="skip the other-configuration leg")
+    ap.add_argument("--no-refined", action="store_true", help="other configurations without the 50M-tet one")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (--gpus must be 1)", file=sys.stderr)
         return 2
 
     # measured in a child process before this one touches the GPU
-    apeak = None if args.no_atomic_peak else atomic_peak()
+    peaks = None if args.no_atomic_peak else atomic_peaks()
+    apeak = peaks.get("fp32c") if peaks else None
 
     import torch
 
@@ -370,9 +450,12 @@ def main() -> int:
                                  out_mass=True)
         assert ctx.sync_status() == simproj.SP_OK, simproj.sp_last_error()
         err64 = abs(float(total64.cpu()[0]) - exact) / exact
-        fp64 = {"value": n / sec64, "ms_per_step": sec64 * 1e3, "mass_rel_err": err64,
-                "clip_ms": prof64["ms_clip"] / max(prof64["calls"], 1),
-                "hbm_gbs": (xyz64.numel() * 8 + simp.numel() * 4 + rho64.numel() * 8 + out64.numel() * 8) / sec64 / 1e9}
+        clip64_s = prof64["ms_clip"] / max(prof64["calls"], 1) * 1e-3
+        apk64 = peaks.get("fp64") if peaks else None
+        fp64 = {"value": n / sec64, "ms_per_step": sec64 * 1e3, "mass_rel_err": err64, "clip_ms": clip64_s * 1e3,
+                "hbm_gbs": (xyz64.numel() * 8 + simp.numel() * 4 + rho64.numel() * 8 + out64.numel() * 8) / sec64 / 1e9,
+                "alu_frac": pieces * FLOPS_PER_PIECE / clip64_s / 1e12 / PEAK_FP64_TFLOPS,
+                "atomic_frac": pieces / clip64_s / apk64 if apk64 else None}
         log(f"fp64: {sec64 * 1e3:.3f} ms/step, {n / sec64:.3e} tets/s, mass err {err64:.2e}")
         del xyz64, rho64, out64
 
@@ -380,10 +463,12 @@ def main() -> int:
     vdens = None if args.no_vertex_density else vertex_density_leg(ctx, max(1, args.steps), 1)
     accur = None if args.no_accuracy else accuracy_leg(ctx, max(1, min(args.steps, 5)), 1)
     amr = None if args.no_amr else amr_leg(ctx, max(1, min(args.steps, 5)), 1)
+    configs = None if args.no_configs else configs_leg(ctx, max(1, min(args.steps, 3)), 1, peaks,
+                                                      refined=not args.no_refined)
 
     traffic, traffic_src = clip_traffic()
     deposits_per_s = pieces / (clip_ms * 1e-3)
-    log(f"traffic: {traffic} ({traffic_src}); atomic peak {apeak}")
+    log(f"traffic: {traffic} ({traffic_src}); atomic peaks {peaks}")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -433,6 +518,7 @@ def main() -> int:
         "vertex_density": vdens,
         "accuracy_control": accur,
         "two_stage": amr,
+        "configs": configs,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -225,8 +225,10 @@ sp_status sp_sync_status(sp_ctx *ctx, void *stream);
 sp_status sp_autotune(sp_ctx *ctx, int dim, const sp_problem *sample, int n, sp_precision prec,
                       const char *cache_path);
 
-/* The launch parameters in use: x-slabs per work item and clip blocks per
- * CU (0: as many as fit on a CU).  Either pointer may be NULL. */
+/* The launch parameters in use: the most x-slabs per work item and clip
+ * blocks per CU (0: as many as fit on a CU).  Either pointer may be NULL.
+ * (A big simplex is cut into work items of fewer slabs, each of about one
+ * lane's expected share of the launch's pieces; the slab group caps that.) */
 sp_status sp_tuning_read(sp_ctx *ctx, int *slab_group, int *blocks_per_cu);
 
 /* Set the launch parameters by hand (slab_group in 1..4095, blocks_per_cu

@@ -1,12 +1,13 @@
 // Measured peaks of the two device resources the projection leans on, for
 // the roofline figures: HBM bandwidth (a plain copy kernel of known size,
 // also the calibration run for the FETCH_SIZE / WRITE_SIZE counters) and the
-// rate of FP32 atomic adds to scattered addresses of a large grid (the
-// deposit's access pattern).
+// rate of atomic adds to scattered addresses of a large grid (the deposit's
+// access pattern).
 //
 //   mbench copy   <MiB> [reps]   stream MiB of float4 from one buffer to another
-//   mbench atomic <MiB> [reps]   FP32 atomic adds to random cells of a MiB grid,
-//                                returning + compensated (as the deposit) and plain
+//   mbench atomic <MiB> [reps]   atomic adds to random cells of a MiB grid:
+//                                FP32 plain, FP32 returning + compensated (as the
+//                                FP32 deposit) and FP64 plain (as the FP64 deposit)
 //
 // Each mode prints one JSON line per measurement.
 #include <hip/hip_runtime.h>
@@ -51,7 +52,7 @@ __global__ void k_atomic(float *hi, float *lo, uint32_t n, int iters)
     for (int i = 0; i < iters; ++i) {
         const uint32_t a = mix(t * 131u + (uint32_t)i * 7919u) % n;
         const float x = 1e-3f * (float)((t + i) & 7);
-        if (COMPENSATED) {
+        if constexpr (COMPENSATED) {
             const float old = unsafeAtomicAdd(hi + a, x);
             const float s = old + x;
             const float bb = s - old;
@@ -60,6 +61,15 @@ __global__ void k_atomic(float *hi, float *lo, uint32_t n, int iters)
         } else {
             unsafeAtomicAdd(hi + a, x);
         }
+    }
+}
+
+__global__ void k_atomic64(double *g, uint32_t n, int iters)
+{
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    for (int i = 0; i < iters; ++i) {
+        const uint32_t a = mix(t * 131u + (uint32_t)i * 7919u) % n;
+        unsafeAtomicAdd(g + a, 1e-3 * (double)((t + i) & 7));
     }
 }
 
@@ -111,10 +121,13 @@ int main(int argc, char **argv)
         const uint32_t n = (uint32_t)(bytes / sizeof(float));
         const int blocks = prop.multiProcessorCount * 32, iters = 64;
         const double ops = (double)blocks * 256 * iters;
-        for (int comp = 0; comp < 2; ++comp) {
+        const char *kinds[3] = {"plain", "returning+compensated", "f64"};
+        for (int comp = 0; comp < 3; ++comp) {
             for (int r = 0; r <= reps; ++r) {
                 CHECK(hipEventRecord(e0, 0));
-                if (comp)
+                if (comp == 2)  // the same cells as doubles: the first half of both buffers' bytes
+                    hipLaunchKernelGGL(k_atomic64, dim3(blocks), dim3(256), 0, 0, (double *)hi, n / 2, iters);
+                else if (comp)
                     hipLaunchKernelGGL(k_atomic<true>, dim3(blocks), dim3(256), 0, 0, hi, lo, n, iters);
                 else
                     hipLaunchKernelGGL(k_atomic<false>, dim3(blocks), dim3(256), 0, 0, hi, lo, n, iters);
@@ -125,7 +138,7 @@ int main(int argc, char **argv)
                 if (r > 0)
                     printf("{\"mode\": \"atomic\", \"kind\": \"%s\", \"grid_bytes\": %zu, \"adds\": %.0f, \"ms\": %.4f, "
                            "\"adds_per_s\": %.4e}\n",
-                           comp ? "returning+compensated" : "plain", bytes, ops, ms, ops / (ms * 1e-3));
+                           kinds[comp], bytes, ops, ms, ops / (ms * 1e-3));
             }
         }
         CHECK(hipFree(hi));

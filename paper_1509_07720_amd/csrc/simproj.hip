@@ -75,9 +75,22 @@ struct Ovf {
 };
 
 struct Tuning {
-    int slab_group;   // x-slabs per work item for big simplices
+    int slab_group;   // at most this many x-slabs per work item
     int chunks_per_cu; // persistent blocks per CU in the clip kernel (0: occupancy)
+    int item_pieces;  // expected pieces a work item is cut down to (0: from the launch size)
 };
+
+// Expected pieces per work item: one lane's expected share of the launch
+// (16 pieces per simplex assumed, 9 waves of 64 lanes per CU), within
+// [16, 1024].  Few simplices (big ones, as a rule) are cut into many items
+// so that every lane has work; many small ones stay whole, which saves the
+// per-item set-up and column rebuilds.
+static int auto_item_pieces(int64_t nsimplex, int num_cu)
+{
+    const double lanes = (double)num_cu * 9.0 * 64.0;
+    const double b = 16.0 * (double)nsimplex / lanes;
+    return b < 16.0 ? 16 : (b > 1024.0 ? 1024 : (int)b);
+}
 
 __device__ inline void record_error(ErrState *e, int code)
 {
@@ -191,6 +204,7 @@ struct ProbDev {
     CallState *cs;
     ErrState *es;
     int slab_group;
+    float item_pieces;
     int count_pieces;
     uint32_t *cmax;  // FP32C: per-cell largest contribution (accuracy control), or NULL
 };
@@ -361,14 +375,19 @@ __global__ __launch_bounds__(256) void k_setup(ProbDev<T> p0, Batch b)
             } else {
                 const int a0 = sweep_order(L).ax[0];
                 int sx = D == 3 ? sel3(L.span[0], L.span[1], L.span[2], a0) : L.span[0];
-                int G = p.slab_group;
+                // work items of about item_pieces expected pieces and at
+                // most slab_group slabs: small simplices stay whole, big
+                // ones are spread over many lanes
+                const float est_all = piece_estimate<T, D>(L);
+                const float per_slab = est_all / (float)sx;
+                const int G = (int)fminf((float)p.slab_group, fmaxf(1.0f, floorf(p.item_pieces / per_slab)));
                 int nit = (sx + G - 1) / G;
                 if (nit > 4095) nit = 4095;  // 12-bit field of the item count
                 if (nit > 1) {
                     unsigned old = atomicAdd(&p.cs->extra, (unsigned)(nit - 1));
                     if (old + (unsigned)(nit - 1) > p.extra_cap) nit = 1;
                 }
-                float est = piece_estimate<T, D>(L) / (float)nit;
+                float est = est_all / (float)nit;
                 int cls = 1;
                 while (cls < NCLS - 1 && (float)(1u << cls) < est) ++cls;
                 info = ((uint32_t)cls << 28) | ((uint32_t)nit << 16) | (uint32_t)sx;
@@ -446,8 +465,15 @@ __global__ __launch_bounds__(256) void k_scatter(ProbDev<T> p0, Batch b)
 // the queue state is wave-uniform (ballots, no LDS and no barriers) and the
 // only LDS is each lane's own polytope.  Per loop iteration a busy lane
 // performs one sweep step (a column build if due, then one piece).
+//
+// Waves per SIMD the compiler must leave room for: 3 (at most 168 VGPRs) for
+// the 17-slot FP32 polytopes, whose LDS admits 9 waves per CU; the other
+// forms are bound by their LDS to 2 or fewer anyway.
+template <int D, typename T, int MAXV>
+constexpr int clip_waves_per_simd() { return D == 3 && sizeof(T) == 4 && MAXV <= 17 ? 3 : 1; }
+
 template <int D, typename T, int MAXV, bool SINGLE>
-__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1))) void k_clip(
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(clip_waves_per_simd<D, T, MAXV>()))) void k_clip(
     ProbDev<T> p0, Batch b, int overflow_pass)
 {
     static_assert(WG == 64, "the queue logic assumes one wave per block");
@@ -948,11 +974,13 @@ extern "C" sp_status sp_create(int hip_device, sp_ctx **ctx)
     c->dummy_total = reinterpret_cast<double *>(reinterpret_cast<char *>(st) + 2048);
     (void)hipMemset(st, 0, 4096);
     (void)hipDeviceSynchronize();
-    c->tune.slab_group = 8;
+    c->tune.slab_group = 16;
     c->tune.chunks_per_cu = 0;
+    c->tune.item_pieces = 0;
     // launch-shape overrides for tuning experiments
-    if (const char *e = getenv("SIMPROJ_SLAB_GROUP")) c->tune.slab_group = atoi(e) > 0 ? atoi(e) : 8;
+    if (const char *e = getenv("SIMPROJ_SLAB_GROUP")) c->tune.slab_group = atoi(e) > 0 ? atoi(e) : 16;
     if (const char *e = getenv("SIMPROJ_CLIP_BLOCKS_PER_CU")) c->tune.chunks_per_cu = atoi(e) > 0 ? atoi(e) : 0;
+    if (const char *e = getenv("SIMPROJ_ITEM_PIECES")) c->tune.item_pieces = atoi(e) > 0 ? atoi(e) : 0;
     c->profiling = 0;
     c->prof_calls = 0;
     c->last_clip_blocks = 0;
@@ -1106,7 +1134,9 @@ static sp_status prepare(sp_ctx *ctx, const sp_problem *probs, int n, std::vecto
         if (fp32 && !probs[i].out_lo) lo_cells += nc;
     }
     if (ntotal >= ((int64_t)1 << 31)) return fail(SP_E_INVALID_ARG, "%lld simplices in one launch (limit 2^31)", (long long)ntotal);
-    const unsigned extra_cap = (unsigned)(ntotal / 2 + 4096);
+    // room for the split items: half the simplices plus 2M (16 MB), enough
+    // for ~1.3e8 pieces of big simplices at the default item size
+    const unsigned extra_cap = (unsigned)(ntotal / 2 + (1 << 21));
     const size_t nitems = (size_t)ntotal + extra_cap;
     size_t off = 0;
     const size_t o_tinfo = off;
@@ -1164,6 +1194,7 @@ static sp_status prepare(sp_ctx *ctx, const sp_problem *probs, int n, std::vecto
         p.cs = ctx->cs;
         p.es = ctx->es;
         p.slab_group = ctx->tune.slab_group;
+        p.item_pieces = (float)(ctx->tune.item_pieces > 0 ? ctx->tune.item_pieces : auto_item_pieces(ntotal, ctx->num_cu));
         p.count_pieces = ctx->profiling >= 2;
         p.cmax = nullptr;
     }
@@ -1723,7 +1754,7 @@ extern "C" sp_status sp_profile_read(sp_ctx *ctx, sp_profile *out)
 // Launch parameters the autotuner searches: the slab group (how many
 // x-slabs one work item covers) and the clip blocks per CU (0 = as many as
 // fit).
-static const int kTuneSlab[] = {1, 2, 4, 8, 16};
+static const int kTuneSlab[] = {1, 2, 4, 8, 16, 32};
 static const int kTuneBlocks[] = {0, 16};
 
 // Signature of a tuning sample: what determines the best parameters, not

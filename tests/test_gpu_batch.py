@@ -226,7 +226,7 @@ def test_autotune_picks_candidate_and_caches(ctx, tmp_path):
     old = ctx.tuning()
     try:
         g, c = ctx.autotune(3, [d.rec], precision=prec, cache_path=cache)
-        assert g in (1, 2, 4, 8, 16) and c in (0, 16)
+        assert g in (1, 2, 4, 8, 16, 32) and c in (0, 16)
         lines = open(cache).read().splitlines()
         assert len(lines) == 1 and lines[0].startswith("simproj-tune 1 sig=")
         ctx.set_tuning(3, 2)
