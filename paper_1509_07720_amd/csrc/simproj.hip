@@ -350,7 +350,9 @@ template <int D, typename T, bool BATCH>
 __global__ __launch_bounds__(256) void k_setup(ProbDev<T> p0, Batch b)
 {
     __shared__ unsigned s_hist[NCLS];
+    __shared__ unsigned s_extra, s_extra_base;
     if (threadIdx.x < NCLS) s_hist[threadIdx.x] = 0u;
+    if (threadIdx.x == 0) s_extra = 0u;
     __syncthreads();
     ProbDev<T> p = p0;
     int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -360,10 +362,11 @@ __global__ __launch_bounds__(256) void k_setup(ProbDev<T> p0, Batch b)
         block_problem(b, p, s0, pi);
         s = s0 + threadIdx.x;
     }
+    int nit = 0, sx = 0;  // nit > 0: work items wanted for the clip kernel
+    float est_all = 0.0f;
     if (s < p.n) {
         Local<T> L;
         int st = setup_any<D>(p, s, p.validate != 0, L);
-        uint32_t info = 0u;
         if (st == SETUP_OK) {
             if (L.span[0] == 1 && L.span[1] == 1 && L.span[2] == 1) {
                 // the whole simplex lies in one cell: deposit its mass
@@ -374,24 +377,15 @@ __global__ __launch_bounds__(256) void k_setup(ProbDev<T> p0, Batch b)
                 if (p.count_pieces) atomicAdd(&p.cs->pieces, 1ull);
             } else {
                 const int a0 = sweep_order(L).ax[0];
-                int sx = D == 3 ? sel3(L.span[0], L.span[1], L.span[2], a0) : L.span[0];
+                sx = D == 3 ? sel3(L.span[0], L.span[1], L.span[2], a0) : L.span[0];
                 // work items of about item_pieces expected pieces and at
                 // most slab_group slabs: small simplices stay whole, big
                 // ones are spread over many lanes
-                const float est_all = piece_estimate<T, D>(L);
+                est_all = piece_estimate<T, D>(L);
                 const float per_slab = est_all / (float)sx;
                 const int G = (int)fminf((float)p.slab_group, fmaxf(1.0f, floorf(p.item_pieces / per_slab)));
-                int nit = (sx + G - 1) / G;
+                nit = (sx + G - 1) / G;
                 if (nit > 4095) nit = 4095;  // 12-bit field of the item count
-                if (nit > 1) {
-                    unsigned old = atomicAdd(&p.cs->extra, (unsigned)(nit - 1));
-                    if (old + (unsigned)(nit - 1) > p.extra_cap) nit = 1;
-                }
-                float est = est_all / (float)nit;
-                int cls = 1;
-                while (cls < NCLS - 1 && (float)(1u << cls) < est) ++cls;
-                info = ((uint32_t)cls << 28) | ((uint32_t)nit << 16) | (uint32_t)sx;
-                atomicAdd(&s_hist[cls], (unsigned)nit);
             }
         } else if (p.validate && st == SETUP_BAD_INDEX) {
             record_error(p.es, SP_E_OUT_OF_RANGE);
@@ -402,6 +396,24 @@ __global__ __launch_bounds__(256) void k_setup(ProbDev<T> p0, Batch b)
         } else if (p.validate && st == SETUP_BAD_SPAN) {
             record_error(p.es, SP_E_PERIODIC_SPAN);
             atomicAdd(&p.es->n_bad_span, 1);
+        }
+    }
+    // the block's extra items (beyond one per simplex) are reserved with one
+    // global atomic; a simplex whose share does not fit stays one item
+    unsigned my_extra = 0u;
+    if (nit > 1) my_extra = atomicAdd(&s_extra, (unsigned)(nit - 1));
+    __syncthreads();
+    if (threadIdx.x == 0) s_extra_base = s_extra ? atomicAdd(&p0.cs->extra, s_extra) : 0u;
+    __syncthreads();
+    if (s < p.n) {
+        uint32_t info = 0u;
+        if (nit > 0) {
+            if (nit > 1 && s_extra_base + my_extra + (unsigned)(nit - 1) > p.extra_cap) nit = 1;
+            const float est = est_all / (float)nit;
+            int cls = 1;
+            while (cls < NCLS - 1 && (float)(1u << cls) < est) ++cls;
+            info = ((uint32_t)cls << 28) | ((uint32_t)nit << 16) | (uint32_t)sx;
+            atomicAdd(&s_hist[cls], (unsigned)nit);
         }
         p.tinfo[s] = info;
     }
@@ -421,33 +433,45 @@ __global__ void k_scan(CallState *cs)
     }
 }
 
+// Simplices per thread of k_scatter: a single problem takes 8, so that each
+// block claims its class ranges with 8x fewer global atomics on the 16
+// cursors (their contention set the kernel's time); a batch keeps one, as
+// its blocks follow the per-problem block table of k_setup.
+template <bool BATCH>
+constexpr int scatter_per_thread() { return BATCH ? 1 : 8; }
+
 template <typename T, bool BATCH>
 __global__ __launch_bounds__(256) void k_scatter(ProbDev<T> p0, Batch b)
 {
+    constexpr int IPT = scatter_per_thread<BATCH>();
     __shared__ unsigned s_cnt[NCLS];
     __shared__ unsigned s_base[NCLS];
     if (threadIdx.x < NCLS) s_cnt[threadIdx.x] = 0u;
     __syncthreads();
     ProbDev<T> p = p0;
-    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t s0 = (int64_t)blockIdx.x * blockDim.x * IPT;
     int pi = 0;
-    if constexpr (BATCH) {
-        int64_t s0;
-        block_problem(b, p, s0, pi);
-        s = s0 + threadIdx.x;
+    if constexpr (BATCH) block_problem(b, p, s0, pi);
+    uint32_t info[IPT];
+    unsigned local[IPT];
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+        const int64_t s = s0 + (int64_t)j * blockDim.x + threadIdx.x;
+        info[j] = s < p.n ? p.tinfo[s] : 0u;
+        local[j] = 0u;
+        if (info[j]) local[j] = atomicAdd(&s_cnt[info[j] >> 28], (info[j] >> 16) & 0xfffu);
     }
-    uint32_t info = 0u;
-    if (s < p.n) info = p.tinfo[s];
-    int cls = (int)(info >> 28), nit = (int)((info >> 16) & 0xfffu), sx = (int)(info & 0xffffu);
-    unsigned local = 0;
-    if (info) local = atomicAdd(&s_cnt[cls], (unsigned)nit);
     __syncthreads();
     if (threadIdx.x < NCLS && s_cnt[threadIdx.x])
         s_base[threadIdx.x] = atomicAdd(&p0.cs->cursor[threadIdx.x], s_cnt[threadIdx.x]);
     __syncthreads();
-    if (info) {
-        unsigned pos = s_base[cls] + local;
-        int per = (sx + nit - 1) / nit;
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+        if (!info[j]) continue;
+        const int64_t s = s0 + (int64_t)j * blockDim.x + threadIdx.x;
+        const int cls = (int)(info[j] >> 28), nit = (int)((info[j] >> 16) & 0xfffu), sx = (int)(info[j] & 0xffffu);
+        const unsigned pos = s_base[cls] + local[j];
+        const int per = (sx + nit - 1) / nit;
         for (int k = 0; k < nit; ++k) {
             int sb = k * per;
             int sc = sx - sb < per ? sx - sb : per;
@@ -1233,7 +1257,8 @@ static void enqueue(sp_ctx *ctx, const std::vector<Prepared<T>> &v, const Batch 
         {
             StageTimer t = timer(ST_BIN);
             hipLaunchKernelGGL(k_scan, dim3(1), dim3(64), 0, stream, ctx->cs);
-            if (single) hipLaunchKernelGGL((k_scatter<T, false>), dim3(nb), dim3(256), 0, stream, p0, b);
+            constexpr int ipt = scatter_per_thread<false>();
+            if (single) hipLaunchKernelGGL((k_scatter<T, false>), dim3((nb + ipt - 1) / ipt), dim3(256), 0, stream, p0, b);
             else hipLaunchKernelGGL((k_scatter<T, true>), dim3(nb), dim3(256), 0, stream, p0, b);
         }
         constexpr int MAXV3 = maxv3<T>();
