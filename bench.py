@@ -87,6 +87,16 @@ def clip_traffic():
     return rec["fetch_kib"] * 1024.0 * f_scale + rec["write_kib"] * 1024.0 * w_scale, "counters"
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def atomic_peaks():
     """Measured rates of atomic adds to random cells of a 64 MiB grid (the
     deposit's pattern), from the mbench program: {"fp32c": compensated FP32
@@ -483,10 +493,17 @@ def main() -> int:
         t = time.perf_counter()
         oracle.project(sub, nthreads=threads, coverage=False)
         dt = time.perf_counter() - t
+        # one thread, on a tenth of the sample
+        k1 = max(1, k // 10)
+        sub1 = dict(sub, simplices=np.ascontiguousarray(sub["simplices"][:k1]), rho=np.ascontiguousarray(sub["rho"][:k1]))
+        t = time.perf_counter()
+        oracle.project(sub1, nthreads=1, coverage=False)
+        dt1 = time.perf_counter() - t
         cpu = {"value": k / dt, "unit": "simplices/s", "cores": threads, "kind": "oracle",
                "sample": f"first {k} tets of the workload, FP64 brute-force clip of every candidate cell, "
-                         f"{dt:.1f} s wall on {threads} threads"}
-        log(f"cpu oracle: {k / dt:.3e} tets/s on {threads} threads ({dt:.1f}s)")
+                         f"{dt:.1f} s wall on {threads} threads",
+               "single_thread_value": k1 / dt1, "cpu_model": cpu_model()}
+        log(f"cpu oracle: {k / dt:.3e} tets/s on {threads} threads ({dt:.1f}s), {k1 / dt1:.3e} on one")
 
     line = {
         "metric": "simplices projected/sec + HBM GB/s at 10M tets->256^3, FP32 vs FP64 at stated error",
