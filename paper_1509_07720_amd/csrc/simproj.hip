@@ -45,7 +45,7 @@ template <typename T>
 constexpr int maxv3() { return sizeof(T) == 4 ? 17 : 18; }
 constexpr int MAXV3_BIG = 32;
 constexpr int MAXP2 = 12;    // polygon vertices per lane and buffer (peak 8)
-constexpr int OVF_CAP = 1 << 16;
+constexpr int OVF_CAP = 1 << 20;  // overflow records per launch (24 MB of scratch)
 
 // Per-call device state, cleared at the start of every call.
 struct CallState {
