@@ -18,7 +18,12 @@ COMMON_FLAGS = [
     # FP32 forms are used)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]
-HIPCC_FLAGS = COMMON_FLAGS + ["-fPIC", "-shared"]
+HIPCC_FLAGS = COMMON_FLAGS + [
+    "-fPIC", "-shared",
+    # the machine scheduler's instruction-level-parallelism strategy: the
+    # FP64 clip kernel measured 2-3 % faster with it, FP32C unchanged
+    "-mllvm", "-amdgpu-sched-strategy=max-ilp",
+]
 
 
 def hipcc() -> str:
@@ -40,11 +45,12 @@ KERNEL_SOURCES = ("simproj.hip", "sp_poly.h", "sp_setup.h")
 
 
 def kernel_source_hash() -> str:
-    """SHA-256 of the projection kernels' sources: counter figures taken on
-    one version of the kernels are only valid while this stays the same."""
+    """SHA-256 of the projection kernels' sources and compiler flags: counter
+    figures taken on one version of the kernels are only valid while this
+    stays the same."""
     import hashlib
 
-    h = hashlib.sha256()
+    h = hashlib.sha256(" ".join(HIPCC_FLAGS).encode())
     for name in KERNEL_SOURCES:
         with open(os.path.join(HERE, "csrc", name), "rb") as f:
             h.update(name.encode() + b"\0" + f.read())
