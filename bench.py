@@ -11,8 +11,10 @@ timed region.  The same workload is also timed in FP64 mode.
 
 Also reported (not part of `value`): the per-vertex density estimate on the
 64^3 lattice, the accuracy-controlled projection of cancelling densities
-against plain FP32C and FP64, and the two-stage (coarsened + donor-cell)
-projection against the exact one.  With --batch, the batched workload (64
+against plain FP32C and FP64, the two-stage (coarsened + donor-cell)
+projection against the exact one, the other 3D configurations with their
+roofline fractions, and the paper's corner-sum formulation against the
+clipping projection.  With --batch, the batched workload (64
 Zel'dovich meshes of 1e4..2e6 tets onto grids of 32^3..256^3) is also timed:
 one captured graph launch for all 64 problems against 64 sequential calls,
 in FP32C and FP64.
@@ -293,6 +295,19 @@ def amr_leg(ctx, steps, warmup):
     return res
 
 
+_REFINED = []
+
+
+def refined_mesh():
+    """The two-level refined 128^3 lattice onto 512^3 (50.3M tets), generated
+    once per run (about a minute of CPU)."""
+    from paper_1509_07720_amd import synth
+
+    if not _REFINED:
+        _REFINED.append(synth.refined_3d(n=128, grid=512, sigma_cells=4.0, seed=5))
+    return _REFINED[0]
+
+
 def configs_leg(ctx, steps, warmup, peaks, refined=True):
     """The other 3D configurations, each in FP32C and FP64: the 64^3
     Zel'dovich lattice onto 128^3 (1.57M tets, per-vertex densities) and the
@@ -308,8 +323,7 @@ def configs_leg(ctx, steps, warmup, peaks, refined=True):
 
     work = [("zeldovich-64^3-lattice-to-128^3", lambda: synth.zeldovich_3d(n=64, grid=128, sigma_cells=1.5, seed=2))]
     if refined:
-        work.append(("refined-128^3-kuhn-2-levels-to-512^3",
-                     lambda: synth.refined_3d(n=128, grid=512, sigma_cells=4.0, seed=5)))
+        work.append(("refined-128^3-kuhn-2-levels-to-512^3", refined_mesh))
     dev = torch.device("cuda:0")
     res = {}
     for name, gen in work:
@@ -365,6 +379,60 @@ def configs_leg(ctx, steps, warmup, peaks, refined=True):
     return res
 
 
+def corner_leg(ctx, steps, warmup):
+    """The paper's corner-sum formulation (sp_project_tets_corners, FP64)
+    against the clipping projection in FP64 and FP32C, on the 64^3
+    Zel'dovich lattice onto 128^3 and on every 64th tetrahedron of the
+    two-level refined 128^3 lattice onto 512^3 (786,432 tets): time per call
+    and the largest cell difference from the FP64 clipping result relative
+    to the largest cell."""
+    import torch
+
+    from paper_1509_07720_amd import synth
+
+    work = [("zeldovich-64^3-lattice-to-128^3", lambda: synth.zeldovich_3d(n=64, grid=128, sigma_cells=1.5, seed=2)),
+            ("refined-128^3-every-64th-tet-to-512^3",
+             lambda: synth.subset(refined_mesh(), 64))]
+    dev = torch.device("cuda:0")
+    res = {}
+    for name, gen in work:
+        prob = gen()
+        dims = [int(d) for d in prob["dims"]]
+        pc = bool(prob["rho_per_corner"])
+        s = torch.from_numpy(np.ascontiguousarray(prob["simplices"], dtype=np.int32)).to(dev)
+        x64 = torch.from_numpy(np.ascontiguousarray(prob["xyz"], dtype=np.float64)).to(dev)
+        r64 = torch.from_numpy(np.ascontiguousarray(prob["rho"], dtype=np.float64)).to(dev)
+        x32, r32 = x64.float(), r64.float()
+        runs = {
+            "corners_fp64": lambda: ctx.project_corners(x64, s, r64, dims, rho_per_corner=pc, out_mass=True),
+            "clip_fp64": lambda: ctx.project(x64, s, r64, dims, precision="fp64", rho_per_corner=pc, out_mass=True),
+            "clip_fp32c": lambda: ctx.project(x32, s, r32, dims, precision="fp32c", rho_per_corner=pc, out_mass=True),
+        }
+        row = {"n_simplex": int(s.shape[0]), "grid": dims}
+        grids = {}
+        for k, fn in runs.items():
+            for _ in range(warmup):
+                fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                g, _ = fn()
+            torch.cuda.synchronize()
+            sec = (time.perf_counter() - t0) / steps
+            st = ctx.sync_status()
+            grids[k] = g.double()
+            row[k] = {"ms": sec * 1e3, "simplices_per_s": s.shape[0] / sec, "status": int(st)}
+            log(f"corner leg {name} {k}: {sec * 1e3:.2f} ms (status {st})")
+        ref = grids["clip_fp64"]
+        scale = float(ref.abs().max())
+        for k in ("corners_fp64", "clip_fp32c"):
+            row[k]["max_cell_diff_rel"] = float((grids[k] - ref).abs().max()) / scale
+        res[name] = row
+        del grids, s, x64, r64, x32, r32
+        torch.cuda.empty_cache()
+    return res
+
+
 def time_steps(ctx, args_dev, steps, warmup, prec):
     import torch
 
@@ -401,6 +469,7 @@ def main() -> int:
     ap.add_argument("--no-amr", action="store_true", help="skip the two-stage projection leg")
     ap.add_argument("--no-configs", action="store_true", help="skip the other-configuration leg")
     ap.add_argument("--no-refined", action="store_true", help="other configurations without the 50M-tet one")
+    ap.add_argument("--no-corners", action="store_true", help="skip the corner-sum comparison leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (--gpus must be 1)", file=sys.stderr)
@@ -475,6 +544,7 @@ def main() -> int:
     amr = None if args.no_amr else amr_leg(ctx, max(1, min(args.steps, 5)), 1)
     configs = None if args.no_configs else configs_leg(ctx, max(1, min(args.steps, 3)), 1, peaks,
                                                       refined=not args.no_refined)
+    corners = None if args.no_corners else corner_leg(ctx, max(1, min(args.steps, 3)), 1)
 
     traffic, traffic_src = clip_traffic()
     deposits_per_s = pieces / (clip_ms * 1e-3)
@@ -536,6 +606,7 @@ def main() -> int:
         "accuracy_control": accur,
         "two_stage": amr,
         "configs": configs,
+        "corner_sums": corners,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

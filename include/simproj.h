@@ -168,6 +168,27 @@ sp_status sp_project_tets_accurate(sp_ctx *ctx, const sp_problem *prob, int accu
 sp_status sp_project_tets_amr(sp_ctx *ctx, const sp_problem *prob, sp_precision prec, int max_level,
                               int64_t *level_counts, void *stream);
 
+/* Projection of tetrahedra by first-order corner sums, FP64 (Section 3.1,
+ * eq. eq_firstOrder with the corner terms of eq. eq:E03D and eq:E13D;
+ * Appendix D's four kinds of vertex of a simplex-cell intersection: simplex
+ * corners, edge-face crossings, facet-edge crossings, grid points inside the
+ * simplex).  Every vertex of every piece adds its terms to its cell; no
+ * piece is built.  The same result as sp_project_tets in FP64 mode, by the
+ * paper's own formulation, for comparison of speed and accuracy; the terms
+ * are signed and cancel within a cell (tested to 1e-10 of the cell's
+ * coverage scale, 1e-12 of the total on meshes in general position).
+ *   prob   as for sp_project_tets, with xyz, rho and out in double
+ * Predicates are evaluated in FP64 and need general position with respect
+ * to the grid: a simplex with a corner on a grid plane (lattice-aligned
+ * meshes, FP32 inputs) is moved with its density by a generic offset of
+ * about 1e-12 cells, which changes its pieces by about that fraction of a
+ * cell and its total not at all; a facet through a grid point or a grid
+ * line through a facet's boundary that remains is summed anyway and
+ * reported by sp_sync_status as SP_E_UNSUPPORTED (count in the message).
+ * A simplex whose bounding box holds more than 2^24 cells is skipped and
+ * reported the same way (one thread enumerates its cells). */
+sp_status sp_project_tets_corners(sp_ctx *ctx, const sp_problem *prob, void *stream);
+
 /* Project n independent problems of dimension `dim` (2 or 3; 1 <= n <=
  * 65535, n == 0 is a no-op) in one persistent, work-stealing
  * launch; `probs` is a HOST array of n problems whose buffers are device

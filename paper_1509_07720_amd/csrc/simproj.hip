@@ -28,6 +28,7 @@
 #include <vector>
 
 #include "simproj.h"
+#include "sp_corner.h"
 #include "sp_setup.h"
 
 using namespace sp;
@@ -68,6 +69,7 @@ struct ErrState {
     int n_bad_span;
     int n_overflow;
     int n_internal;
+    int n_degenerate;  // corner sums: configurations outside general position
 };
 
 struct Ovf {
@@ -618,6 +620,35 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(clip_waves_p
                 record_error(p.es, SP_E_INTERNAL);
                 atomicAdd(&p.es->n_internal, 1);
             }
+        }
+    }
+}
+
+// Projection by first-order corner sums (Section 3.1, Appendix D), FP64:
+// one thread per simplex enumerates the vertices of all its cell pieces
+// (simplex corners, edge-face and facet-edge crossings, grid points inside)
+// and adds each vertex's terms to its cell(s).  Grid-stride over simplices.
+__global__ __launch_bounds__(256) void k_corner(ProbDev<double> p)
+{
+    const int64_t st = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < p.n; s += st) {
+        Local<double> L;
+        const int r = setup_any<3>(p, s, p.validate != 0, L);
+        if (r == SETUP_OK) {
+            auto dep = make_dep<double>(p, L, kIdentity);
+            if (corner_project(L, dep) > 0) {
+                record_error(p.es, SP_E_UNSUPPORTED);
+                atomicAdd(&p.es->n_degenerate, 1);
+            }
+        } else if (p.validate && r == SETUP_BAD_INDEX) {
+            record_error(p.es, SP_E_OUT_OF_RANGE);
+            atomicAdd(&p.es->n_bad_index, 1);
+        } else if (p.validate && r == SETUP_NONFINITE) {
+            record_error(p.es, SP_E_NONFINITE);
+            atomicAdd(&p.es->n_nonfinite, 1);
+        } else if (p.validate && r == SETUP_BAD_SPAN) {
+            record_error(p.es, SP_E_PERIODIC_SPAN);
+            atomicAdd(&p.es->n_bad_span, 1);
         }
     }
 }
@@ -1323,6 +1354,33 @@ extern "C" sp_status sp_project_tets(sp_ctx *ctx, const sp_problem *prob, sp_pre
     return prec == SP_PREC_FP32C ? project_impl<3, float>(ctx, prob, s) : project_impl<3, double>(ctx, prob, s);
 }
 
+// Projection by corner sums (FP64): the same result as sp_project_tets in
+// FP64 mode, by the paper's own formulation, for comparison.
+extern "C" sp_status sp_project_tets_corners(sp_ctx *ctx, const sp_problem *prob, void *stream)
+{
+    sp_status st = check_problem(prob, 3, SP_PREC_FP64);
+    if (st != SP_OK) return st;
+    if (!ctx) return fail(SP_E_INVALID_ARG, "ctx is NULL");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    HIPCHECK(hipSetDevice(ctx->device));
+    std::vector<Prepared<double>> v;
+    int64_t ntotal = 0;
+    st = prepare<3, double>(ctx, prob, 1, v, ntotal);
+    if (st != SP_OK) return st;
+    const Prepared<double> &q = v[0];
+    hipLaunchKernelGGL(k_clear_state, dim3(1), dim3(64), 0, s, ctx->cs, q.total);
+    if (!q.accumulate)
+        hipLaunchKernelGGL(k_fill<double>, dim3(grid_blocks(q.ncell, 256)), dim3(256), 0, s, q.p.out, q.ncell);
+    if (ntotal > 0)
+        hipLaunchKernelGGL(k_corner, dim3(grid_blocks((size_t)ntotal, 256)), dim3(256), 0, s, q.p);
+    if (q.total)
+        hipLaunchKernelGGL(k_finalize<double>, dim3(grid_blocks(q.ncell, 256 * 8)), dim3(256), 0, s, q.p.out, nullptr,
+                           0, q.ncell, q.to_mass, q.total);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(SP_E_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+    return SP_OK;
+}
+
 extern "C" sp_status sp_project_tris(sp_ctx *ctx, const sp_problem *prob, sp_precision prec, void *stream)
 {
     sp_status st = check_problem(prob, 2, prec);
@@ -1717,8 +1775,9 @@ extern "C" sp_status sp_sync_status(sp_ctx *ctx, void *stream)
     HIPCHECK(hipMemset(ctx->es, 0, sizeof e));
     if (e.first != 0) {
         return fail((sp_status)e.first,
-                    "device errors: %d bad index, %d non-finite, %d periodic span, %d internal (%d overflow retries)",
-                    e.n_bad_index, e.n_nonfinite, e.n_bad_span, e.n_internal, e.n_overflow);
+                    "device errors: %d bad index, %d non-finite, %d periodic span, %d internal (%d overflow retries), "
+                    "%d simplices outside general position (corner sums)",
+                    e.n_bad_index, e.n_nonfinite, e.n_bad_span, e.n_internal, e.n_overflow, e.n_degenerate);
     }
     return SP_OK;
 }

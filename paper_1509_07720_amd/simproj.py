@@ -79,6 +79,8 @@ _lib.sp_project_tets_accurate.restype = ctypes.c_int
 _lib.sp_project_tets_amr.argtypes = [_V, ctypes.POINTER(sp_problem), ctypes.c_int, ctypes.c_int,
                                      ctypes.POINTER(ctypes.c_int64), _V]
 _lib.sp_project_tets_amr.restype = ctypes.c_int
+_lib.sp_project_tets_corners.argtypes = [_V, ctypes.POINTER(sp_problem), _V]
+_lib.sp_project_tets_corners.restype = ctypes.c_int
 _lib.sp_project_batch.argtypes = [_V, ctypes.c_int, ctypes.POINTER(sp_problem), ctypes.c_int, ctypes.c_int, _V]
 _lib.sp_project_batch.restype = ctypes.c_int
 _lib.sp_sync_status.argtypes = [_V, _V]
@@ -139,6 +141,10 @@ def sp_project_tets_accurate(ctx, prob: sp_problem, accurate_bits: int, wrong_bi
     counts = (ctypes.c_int64 * 2)()
     st = _lib.sp_project_tets_accurate(ctx, ctypes.byref(prob), int(accurate_bits), int(wrong_bits), counts, stream)
     return st, counts[0], counts[1]
+
+
+def sp_project_tets_corners(ctx, prob: sp_problem, stream=None) -> int:
+    return _lib.sp_project_tets_corners(ctx, ctypes.byref(prob), stream)
 
 
 def sp_project_tets_amr(ctx, prob: sp_problem, prec: int, max_level: int, stream=None):
@@ -282,6 +288,29 @@ class Context:
                          out_mass, accumulate, validate)
         fn = sp_project_tets if dim == 3 else sp_project_tris
         _check(fn(self.handle, p, prec, _stream_ptr(stream)), fn.__name__)
+        return out, total
+
+    def project_corners(self, xyz, simplices, rho, dims, origin=(0.0, 0.0, 0.0), extent=(1.0, 1.0, 1.0),
+                        periodic=(True, True, True), rho_per_corner: bool = False, out=None, out_mass: bool = False,
+                        accumulate: bool = False, validate: bool = False, want_total: bool = True, stream=None):
+        """FP64 projection of tetrahedra by corner sums
+        (sp_project_tets_corners); returns (grid, total_mass)."""
+        import torch
+
+        if xyz.dtype != torch.float64 or rho.dtype != torch.float64:
+            raise TypeError("xyz and rho must be float64 for the corner-sum projection")
+        if simplices.dtype != torch.int32 or int(xyz.shape[1]) != 3:
+            raise TypeError("simplices must be int32 tetrahedra")
+        for t in (xyz, simplices, rho):
+            if not t.is_cuda or not t.is_contiguous():
+                raise ValueError("inputs must be contiguous device tensors")
+        shape = tuple(int(d) for d in reversed(list(dims)[:3]))
+        if out is None:
+            out = torch.empty(shape, dtype=torch.float64, device=xyz.device)
+        total = torch.zeros(1, dtype=torch.float64, device=xyz.device) if want_total else None
+        p = make_problem(xyz, simplices, rho, dims, origin, extent, periodic, rho_per_corner, out, None, total,
+                         out_mass, accumulate, validate)
+        _check(sp_project_tets_corners(self.handle, p, _stream_ptr(stream)), "sp_project_tets_corners")
         return out, total
 
     def vertex_density(self, xyz, simplices, mass=None, mass_uniform: float = 1.0, extent=(1.0, 1.0, 1.0),

@@ -22,7 +22,7 @@ def test_header_declares_the_boundary():
     names = _declared()
     for n in ("sp_create", "sp_destroy", "sp_project_tets", "sp_project_tris", "sp_project_batch",
               "sp_sync_status", "sp_autotune", "sp_last_error", "sp_vertex_density", "sp_tuning_set",
-              "sp_tuning_read", "sp_project_tets_accurate", "sp_project_tets_amr"):
+              "sp_tuning_read", "sp_project_tets_accurate", "sp_project_tets_amr", "sp_project_tets_corners"):
         assert n in names
 
 
@@ -177,3 +177,15 @@ def test_amr_host_validation():
     assert st == simproj.SP_E_INVALID_ARG and "max_level" in simproj.sp_last_error()
     st, _ = simproj.sp_project_tets_amr(None, p, simproj.SP_PREC_FP32C, 4)  # dims 8 not a multiple of 16
     assert st == simproj.SP_E_INVALID_ARG and "multiple" in simproj.sp_last_error()
+
+
+def test_corners_host_validation():
+    from paper_1509_07720_amd import simproj
+
+    p = _prob()
+    assert simproj.sp_project_tets_corners(None, p) == simproj.SP_E_INVALID_ARG
+    assert "ctx is NULL" in simproj.sp_last_error()
+    p = _prob()
+    p.grid.dims[1] = 0
+    assert simproj.sp_project_tets_corners(None, p) == simproj.SP_E_INVALID_ARG
+    assert "dims[1]" in simproj.sp_last_error()

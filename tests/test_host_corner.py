@@ -1,0 +1,67 @@
+"""The corner-sum projection (the header the corner kernel uses) compiled
+for the host with g++ and compared with the oracle on the CPU: meshes in
+general position, and meshes with corners on grid planes (which the sum
+moves off them by a generic offset of about 1e-12 cells), must match to the
+corner-sum tolerance."""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1509_07720_amd import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+# Corner sums are signed and cancel within a cell; see DESIGN (corner sums)
+# for the tolerance: per cell relative to the coverage scale, and of the total.
+TOL_CELL, TOL_MASS = 1e-10, 1e-12
+
+
+@pytest.fixture(scope="module")
+def lib(tmp_path_factory):
+    so = str(tmp_path_factory.mktemp("corner") / "corner_host.so")
+    subprocess.check_call(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-I", os.path.join(ROOT, "include"), "-I",
+                           os.path.join(ROOT, "paper_1509_07720_amd", "csrc"), "-o", so,
+                           os.path.join(ROOT, "tests", "host", "corner_host.cpp")])
+    L = ctypes.CDLL(so)
+    V = ctypes.c_void_p
+    L.corner_host.argtypes = [V, ctypes.c_int64, V, ctypes.c_int64, V, ctypes.c_int, V, V, V, V]
+    return L
+
+
+def corner(lib, prob):
+    x = np.ascontiguousarray(prob["xyz"], np.float64)
+    s = np.ascontiguousarray(prob["simplices"], np.int32)
+    r = np.ascontiguousarray(prob["rho"], np.float64)
+    dims = np.asarray(prob["dims"], np.int32)
+    per = np.asarray([1 if p else 0 for p in prob["periodic"]], np.int32)
+    out = np.zeros(int(np.prod(dims)), np.float64)
+    st = np.zeros(4, np.int64)
+    lib.corner_host(x.ctypes.data, x.shape[0], s.ctypes.data, s.shape[0], r.ctypes.data, int(prob["rho_per_corner"]),
+                    dims.ctypes.data, per.ctypes.data, out.ctypes.data, st.ctypes.data)
+    return out.reshape(tuple(dims[::-1])), st
+
+
+PROBLEMS = {
+    "lattice_3d": lambda: synth.zeldovich_3d(n=12, grid=24, sigma_cells=1.5, seed=2),
+    "lattice_per_corner": lambda: synth.zeldovich_3d(n=8, grid=20, sigma_cells=1.0, seed=6, per_corner=True),
+    "soup": lambda: synth.tet_soup(n_tets=3000, grid=32, seed=5),
+    "refined": lambda: synth.refined_3d(n=6, grid=32, sigma_cells=1.0, seed=5),
+    # FP32 coordinates on a grid of 48: some corners fall exactly on grid planes
+    "soup_on_planes": lambda: synth.tet_soup(n_tets=20000, grid=48, seed=5),
+    # every corner on a grid point
+    "undisplaced_lattice": lambda: synth.zeldovich_3d(n=8, grid=16, sigma_cells=0.0, seed=1),
+}
+
+
+@pytest.mark.parametrize("name", list(PROBLEMS))
+def test_corner_sums_match_oracle(lib, name):
+    prob = PROBLEMS[name]()
+    got, st = corner(lib, prob)
+    assert st[2] == 0  # general position
+    err = oracle.cell_error(got, oracle.project(prob))
+    assert err["e_cell"] <= TOL_CELL, err
+    assert err["e_mass"] <= TOL_MASS, err
