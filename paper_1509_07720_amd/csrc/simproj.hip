@@ -628,7 +628,10 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(clip_waves_p
 // one thread per simplex enumerates the vertices of all its cell pieces
 // (simplex corners, edge-face and facet-edge crossings, grid points inside)
 // and adds each vertex's terms to its cell(s).  Grid-stride over simplices.
-__global__ __launch_bounds__(256) void k_corner(ProbDev<double> p)
+// The kernel waits on memory far more than it computes; held to 2 waves
+// per SIMD (128 VGPRs, the rest spilled) it ran 1.7x faster than at 1 wave
+// with 256 VGPRs, and 3 or 4 waves ran slower again.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_corner(ProbDev<double> p)
 {
     const int64_t st = (int64_t)gridDim.x * blockDim.x;
     for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < p.n; s += st) {

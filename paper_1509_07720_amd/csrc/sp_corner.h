@@ -47,11 +47,15 @@ SP_HD inline double comp(D3 a, int d) { return d == 0 ? a.x : (d == 1 ? a.y : a.
 SP_HD inline D3 axis(int d, double s) { return d3(d == 0 ? s : 0.0, d == 1 ? s : 0.0, d == 2 ? s : 0.0); }
 
 // The corner terms of one vertex: edges t[0..2], facets with inward normals
-// b[0..2], facet f holding edges fe[f][0] and fe[f][1].
+// b[0..2], facet f holding edges fe[f][0] and fe[f][1].  The fixed-count
+// loops here and below are unrolled so that these small arrays are indexed
+// by constants (registers, not scratch memory).
 SP_HD inline double vertex_terms(D3 P, double rho0, D3 g, const D3 *t, const D3 *b, const int (*fe)[2])
 {
     double s = 0.0;
+#pragma unroll
     for (int f = 0; f < 3; ++f) {
+#pragma unroll
         for (int k = 0; k < 2; ++k) {
             const D3 T = t[fe[f][k]];
             const D3 other = t[fe[f][1 - k]];
@@ -135,6 +139,7 @@ SP_HD inline int corner_project(const Local<double> &L, Dep &dep)
 
     // A: every simplex corner, in its own cell; facet k of the corner's
     // cone is the simplex facet opposite the corner's edge k
+#pragma unroll
     for (int a = 0; a < 4; ++a) {
         int o3[3], n = 0;
         for (int k = 0; k < 4; ++k)
@@ -152,7 +157,9 @@ SP_HD inline int corner_project(const Local<double> &L, Dep &dep)
 
     // B: every edge through every grid plane it crosses; the crossing point
     // is a vertex of the pieces on both sides of the plane
+#pragma unroll
     for (int a = 0; a < 3; ++a) {
+#pragma unroll
         for (int bq = a + 1; bq < 4; ++bq) {
             int m1 = -1, m2 = -1;
             for (int k = 0; k < 4; ++k)
@@ -190,6 +197,7 @@ SP_HD inline int corner_project(const Local<double> &L, Dep &dep)
 
     // C: every facet through every cell edge (grid line) it crosses; the
     // crossing is a vertex of the four pieces around that line
+#pragma unroll
     for (int m = 0; m < 4; ++m) {
         const int ia = (m + 1) & 3, ib = (m + 2) & 3, ic = (m + 3) & 3;
         const D3 nF = nf[m];
@@ -253,6 +261,7 @@ SP_HD inline int corner_project(const Local<double> &L, Dep &dep)
                     in = sd > 0.0;
                 }
                 if (!in) continue;
+#pragma unroll
                 for (int c = 0; c < 8; ++c) {
                     const int dx = c & 1, dy = (c >> 1) & 1, dz = (c >> 2) & 1;
                     const D3 t[3] = {axis(0, dx ? -1.0 : 1.0), axis(1, dy ? -1.0 : 1.0), axis(2, dz ? -1.0 : 1.0)};
