@@ -119,9 +119,11 @@ def atomic_peaks():
     return peak
 
 
-def batch_leg(ctx, steps, warmup):
+def batch_leg(ctx, steps, warmup, peaks=None):
     """The batched workload: one graph launch for 64 problems against 64
-    sequential calls; FP32C and FP64."""
+    sequential calls; FP32C and FP64.  With the pieces counted one problem
+    at a time (untimed), the batched launch's ALU, HBM and atomic fractions
+    as for the other workloads, over the whole launch."""
     import torch
 
     from paper_1509_07720_amd import simproj, synth
@@ -153,11 +155,21 @@ def batch_leg(ctx, steps, warmup):
             for r in recs:
                 simproj._check(simproj.sp_project_tets(ctx.handle, r, code, stream), "sp_project_tets")
 
+        pieces = 0
+        ctx.profile(2)
+        for r in recs:
+            simproj._check(simproj.sp_project_tets(ctx.handle, r, code, stream), "sp_project_tets")
+            torch.cuda.synchronize()
+            pieces += ctx.profile_read()["pieces"]
+        ctx.profile(0)
+        nb = 4 if prec == "fp32c" else 8
+        algo = sum(k[0].numel() * nb + k[1].numel() * 4 + k[2].numel() * nb + k[3].numel() * 8
+                   for k in keep)
         t = time.perf_counter()
         batched()  # first call: capture and instantiation
         torch.cuda.synchronize()
         first = time.perf_counter() - t
-        row = {"first_call_ms": first * 1e3}
+        row = {"first_call_ms": first * 1e3, "pieces": pieces}
         for name, fn in (("batched", batched), ("sequential", sequential)):
             for _ in range(warmup):
                 fn()
@@ -168,6 +180,12 @@ def batch_leg(ctx, steps, warmup):
             torch.cuda.synchronize()
             sec = (time.perf_counter() - t) / steps
             row[name] = {"ms_per_step": sec * 1e3, "value": res["n_simplex"] / sec}
+        sec = row["batched"]["ms_per_step"] * 1e-3
+        peak_alu = PEAK_FP32_TFLOPS if prec == "fp32c" else PEAK_FP64_TFLOPS
+        apk = peaks.get(prec) if peaks else None
+        row["batched"].update({"alu_frac": pieces * FLOPS_PER_PIECE / sec / 1e12 / peak_alu,
+                               "hbm_frac": algo / sec / 1e9 / PEAK_HBM_GBS,
+                               "atomic_frac": pieces / sec / apk if apk else None})
         res[prec] = row
         log(f"batch {prec}: batched {row['batched']['ms_per_step']:.1f} ms, "
             f"sequential {row['sequential']['ms_per_step']:.1f} ms, first call {first * 1e3:.0f} ms")
@@ -538,7 +556,7 @@ def main() -> int:
         log(f"fp64: {sec64 * 1e3:.3f} ms/step, {n / sec64:.3e} tets/s, mass err {err64:.2e}")
         del xyz64, rho64, out64
 
-    batch = batch_leg(ctx, max(1, min(args.steps, 3)), 1) if args.batch else None
+    batch = batch_leg(ctx, max(1, min(args.steps, 3)), 1, peaks) if args.batch else None
     vdens = None if args.no_vertex_density else vertex_density_leg(ctx, max(1, args.steps), 1)
     accur = None if args.no_accuracy else accuracy_leg(ctx, max(1, min(args.steps, 5)), 1)
     amr = None if args.no_amr else amr_leg(ctx, max(1, min(args.steps, 5)), 1)
