@@ -141,6 +141,37 @@ struct DepF32 {
         float err = (old - (s - bb)) + (x - bb);
         if (err != 0.0f) unsafeAtomicAdd(lo + idx, err);
     }
+
+    // Global index of local cell (ix, iy, iz); false outside a non-periodic
+    // grid.  With add(), the two halves of operator() for callers that merge
+    // contributions to one cell first.
+    __device__ bool cell(int ix, int iy, int iz, size_t &idx) const
+    {
+        int c[3] = {anchor[0] + ix, anchor[1] + iy, anchor[2] + iz};
+        for (int d = 0; d < 3; ++d) {
+            if (periodic[d]) {
+                c[d] = c[d] >= dims[d] ? c[d] - dims[d] : c[d];
+            } else if ((unsigned)c[d] >= (unsigned)dims[d]) {
+                return false;
+            }
+        }
+        idx = (size_t)c[0] * stride[0] + (size_t)c[1] * stride[1] + (size_t)c[2] * stride[2];
+        return true;
+    }
+    __device__ void add(size_t idx, double v) const
+    {
+        // the FP64 value as a float and the float remainder: the remainder
+        // joins the low grid with the rounding error of the high sum
+        const double w = v * (double)scale;
+        const float x = (float)w;
+        const float rem = (float)(w - (double)x);
+        if (cmax) atomicMax(cmax + idx, __float_as_uint(fabsf(x)));
+        float old = unsafeAtomicAdd(hi + idx, x);
+        float s = old + x;
+        float bb = s - old;
+        float err = (old - (s - bb)) + (x - bb) + rem;
+        if (err != 0.0f) unsafeAtomicAdd(lo + idx, err);
+    }
 };
 
 struct DepF64 {
@@ -170,6 +201,21 @@ struct DepF64 {
         size_t idx = (size_t)c[0] * stride[0] + (size_t)c[1] * stride[1] + (size_t)c[2] * stride[2];
         unsafeAtomicAdd(out + idx, v * scale);
     }
+
+    __device__ bool cell(int ix, int iy, int iz, size_t &idx) const
+    {
+        int c[3] = {anchor[0] + ix, anchor[1] + iy, anchor[2] + iz};
+        for (int d = 0; d < 3; ++d) {
+            if (periodic[d]) {
+                c[d] = c[d] >= dims[d] ? c[d] - dims[d] : c[d];
+            } else if ((unsigned)c[d] >= (unsigned)dims[d]) {
+                return false;
+            }
+        }
+        idx = (size_t)c[0] * stride[0] + (size_t)c[1] * stride[1] + (size_t)c[2] * stride[2];
+        return true;
+    }
+    __device__ void add(size_t idx, double v) const { unsafeAtomicAdd(out + idx, v * scale); }
 };
 
 template <typename T>
@@ -348,13 +394,28 @@ __global__ void k_clear_state(CallState *cs, double *total)
     if (threadIdx.x == 0 && total) *total = 0.0;
 }
 
+// Single-cell simplices of one block are merged per cell before they reach
+// the grid: an open-addressing table in LDS (twice as many slots as
+// threads, so it never fills) of global cell indices and FP64 partial sums;
+// each cell then costs one grid deposit per block instead of one per
+// simplex, which matters where many small simplices share a cell.
+constexpr int SETUP_TABLE = 512;
+constexpr unsigned long long SETUP_EMPTY = ~0ull;
+
 template <int D, typename T, bool BATCH>
 __global__ __launch_bounds__(256) void k_setup(ProbDev<T> p0, Batch b)
 {
+    static_assert(SETUP_TABLE >= 2 * 256, "the merge table needs room for every thread of a block");
     __shared__ unsigned s_hist[NCLS];
     __shared__ unsigned s_extra, s_extra_base;
+    __shared__ unsigned long long s_key[SETUP_TABLE];
+    __shared__ double s_sum[SETUP_TABLE];
     if (threadIdx.x < NCLS) s_hist[threadIdx.x] = 0u;
     if (threadIdx.x == 0) s_extra = 0u;
+    for (int e = threadIdx.x; e < SETUP_TABLE; e += blockDim.x) {
+        s_key[e] = SETUP_EMPTY;
+        s_sum[e] = 0.0;
+    }
     __syncthreads();
     ProbDev<T> p = p0;
     int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -374,8 +435,20 @@ __global__ __launch_bounds__(256) void k_setup(ProbDev<T> p0, Batch b)
                 // the whole simplex lies in one cell: deposit its mass
                 T rs = L.v[0].r + L.v[1].r + L.v[2].r + (D == 3 ? L.v[3].r : T(0));
                 T val = D == 3 ? L.det * rs / T(24) : L.det * rs / T(6);
-                auto dep = make_dep<T>(p, L, kIdentity);
-                dep(0, 0, 0, val);
+                const auto dep = make_dep<T>(p, L, kIdentity);
+                size_t idx;
+                if (dep.cell(0, 0, 0, idx)) {
+                    const unsigned long long key = (unsigned long long)idx;
+                    unsigned h = (unsigned)((key * 0x9E3779B97F4A7C15ull) >> 55) & (SETUP_TABLE - 1);
+                    for (int probe = 0; probe < SETUP_TABLE; ++probe) {
+                        const unsigned long long k = atomicCAS(&s_key[h], SETUP_EMPTY, key);
+                        if (k == SETUP_EMPTY || k == key) {
+                            atomicAdd(&s_sum[h], (double)val);
+                            break;
+                        }
+                        h = (h + 1) & (SETUP_TABLE - 1);
+                    }
+                }
                 if (p.count_pieces) atomicAdd(&p.cs->pieces, 1ull);
             } else {
                 const int a0 = sweep_order(L).ax[0];
@@ -421,6 +494,14 @@ __global__ __launch_bounds__(256) void k_setup(ProbDev<T> p0, Batch b)
     }
     __syncthreads();
     if (threadIdx.x < NCLS && s_hist[threadIdx.x]) atomicAdd(&p0.cs->hist[threadIdx.x], s_hist[threadIdx.x]);
+    // the merged single-cell deposits (every simplex of a block belongs to
+    // one problem, so p's grid is the block's grid; only the grid pointers
+    // and scale of the deposit are used here)
+    Local<T> origin_cell;
+    for (int d = 0; d < 3; ++d) origin_cell.anchor[d] = 0;
+    const auto grid = make_dep<T>(p, origin_cell, kIdentity);
+    for (int e = threadIdx.x; e < SETUP_TABLE; e += blockDim.x)
+        if (s_key[e] != SETUP_EMPTY) grid.add((size_t)s_key[e], s_sum[e]);
 }
 
 __global__ void k_scan(CallState *cs)

@@ -197,6 +197,18 @@ def test_inside_one_cell_and_empty(ctx, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_dense_mesh_single_cell_merge(ctx, prec):
+    """A 32^3 lattice onto 8^3 (384 tets per cell): most tetrahedra lie in one
+    cell and are merged per cell and block before they reach the grid; the
+    result must still match the oracle cell by cell, with signed densities
+    as well (one simplex in ten negative)."""
+    prob = synth.zeldovich_3d(n=32, grid=8, sigma_cells=0.2, seed=12, per_corner=True)
+    rng = np.random.default_rng(12)
+    prob["rho"] = prob["rho"] * np.where(rng.uniform(size=prob["rho"].shape[0]) < 0.1, -1.0, 1.0)[:, None]
+    check(ctx, prob, prec)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
 def test_non_periodic_drops_outside(ctx, prec):
     prob = synth.zeldovich_3d(n=16, grid=24, sigma_cells=1.0, seed=8)
     # shift and shrink so the mesh sticks out of a non-periodic box
