@@ -35,12 +35,18 @@ def _dev(prob):
     return x, s, r
 
 
+def stretched(prob):
+    return dict(prob, xyz=np.asarray(prob["xyz"]) * 1.3 - 0.15, periodic=(False,) * 3)
+
+
 CASES = {
     "lattice_3d": lambda: synth.zeldovich_3d(n=12, grid=24, sigma_cells=1.5, seed=2),
     "lattice_per_corner": lambda: synth.zeldovich_3d(n=8, grid=20, sigma_cells=1.0, seed=6, per_corner=True),
     "soup": lambda: synth.tet_soup(n_tets=20000, grid=48, seed=5),
     "refined": lambda: synth.refined_3d(n=8, grid=48, sigma_cells=1.0, seed=5),
     "undisplaced_lattice": lambda: synth.zeldovich_3d(n=8, grid=16, sigma_cells=0.0, seed=1),
+    # stretched over a non-periodic box: wrapped simplices span it, parts fall outside
+    "non_periodic": lambda: stretched(synth.zeldovich_3d(n=8, grid=16, sigma_cells=1.0, seed=8)),
 }
 
 
@@ -48,7 +54,8 @@ CASES = {
 def test_corners_match_oracle(ctx, name):
     prob = CASES[name]()
     x, s, r = _dev(prob)
-    g, total = ctx.project_corners(x, s, r, list(prob["dims"]), rho_per_corner=prob["rho_per_corner"], out_mass=True)
+    g, total = ctx.project_corners(x, s, r, list(prob["dims"]), periodic=prob["periodic"],
+                                   rho_per_corner=prob["rho_per_corner"], out_mass=True)
     assert ctx.sync_status() == simproj.SP_OK, simproj.sp_last_error()
     ref = oracle.project(prob)
     err = oracle.cell_error(g.cpu().numpy(), ref)

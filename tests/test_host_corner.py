@@ -45,6 +45,10 @@ def corner(lib, prob):
     return out.reshape(tuple(dims[::-1])), st
 
 
+def stretched(prob):
+    return dict(prob, xyz=np.asarray(prob["xyz"]) * 1.3 - 0.15, periodic=(False,) * 3)
+
+
 PROBLEMS = {
     "lattice_3d": lambda: synth.zeldovich_3d(n=12, grid=24, sigma_cells=1.5, seed=2),
     "lattice_per_corner": lambda: synth.zeldovich_3d(n=8, grid=20, sigma_cells=1.0, seed=6, per_corner=True),
@@ -54,6 +58,9 @@ PROBLEMS = {
     "soup_on_planes": lambda: synth.tet_soup(n_tets=20000, grid=48, seed=5),
     # every corner on a grid point
     "undisplaced_lattice": lambda: synth.zeldovich_3d(n=8, grid=16, sigma_cells=0.0, seed=1),
+    # a lattice stretched over a non-periodic box: wrapped simplices span it,
+    # parts fall outside and are dropped
+    "non_periodic": lambda: stretched(synth.zeldovich_3d(n=8, grid=16, sigma_cells=1.0, seed=8)),
 }
 
 
