@@ -397,6 +397,61 @@ def configs_leg(ctx, steps, warmup, peaks, refined=True):
     return res
 
 
+def tris_leg(ctx, steps, warmup):
+    """2D: the two-sine triangle lattice (1024^2 vertices, 2.1M triangles,
+    per-vertex densities) onto 2048^2, FP32C and FP64 (sp_project_tris):
+    time per call, pieces and the error of the total mass."""
+    import torch
+
+    from paper_1509_07720_amd import synth
+
+    prob = synth.as_float32(synth.two_sine_2d(n=1024, grid=2048, seed=1))
+    dims = [int(d) for d in prob["dims"][:2]]
+    exact = float(exact_total_2d(prob))
+    dev = torch.device("cuda:0")
+    s = torch.from_numpy(np.ascontiguousarray(prob["simplices"], dtype=np.int32)).to(dev)
+    res = {"workload": "two-sine-1024^2-lattice-to-2048^2", "n_simplex": int(s.shape[0]), "grid": dims}
+    for prec, dt in (("fp32c", torch.float32), ("fp64", torch.float64)):
+        xyz = torch.from_numpy(np.ascontiguousarray(prob["xyz"])).to(dev, dt)
+        rho = torch.from_numpy(np.ascontiguousarray(prob["rho"])).to(dev, dt)
+        out = torch.empty(tuple(reversed(dims)), dtype=dt, device=dev)
+
+        def call():
+            return ctx.project(xyz, s, rho, dims, precision=prec, out=out, out_mass=True)
+
+        ctx.profile(2)
+        call()
+        pieces = ctx.profile_read()["pieces"]
+        ctx.profile(0)
+        for _ in range(warmup):
+            call()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            call()
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / steps
+        _, total = call()
+        assert ctx.sync_status() == 0
+        res[prec] = {"ms_per_call": sec * 1e3, "simplices_per_s": s.shape[0] / sec, "pieces": pieces,
+                     "mass_rel_err": abs(float(total.cpu()[0]) - exact) / exact}
+        log(f"2d {prec}: {sec * 1e3:.2f} ms/call, {pieces} pieces")
+    return res
+
+
+def exact_total_2d(prob) -> float:
+    """Exact FP64 total of a 2D problem: sum of |area| x mean corner density."""
+    from paper_1509_07720_amd import synth
+
+    P = synth.unwrapped_corners(np.asarray(prob["xyz"]), np.asarray(prob["simplices"]), np.asarray(prob["extent"]),
+                                prob["periodic"])
+    e1, e2 = P[:, 1] - P[:, 0], P[:, 2] - P[:, 0]
+    area = 0.5 * np.abs(e1[:, 0] * e2[:, 1] - e1[:, 1] * e2[:, 0])
+    R = np.asarray(prob["rho"])
+    r = R if prob["rho_per_corner"] else R[np.asarray(prob["simplices"])]
+    return float(np.sum(area * r.mean(axis=1)))
+
+
 def corner_leg(ctx, steps, warmup):
     """The paper's corner-sum formulation (sp_project_tets_corners, FP64)
     against the clipping projection in FP64 and FP32C, on the 64^3
@@ -488,6 +543,7 @@ def main() -> int:
     ap.add_argument("--no-configs", action="store_true", help="skip the other-configuration leg")
     ap.add_argument("--no-refined", action="store_true", help="other configurations without the 50M-tet one")
     ap.add_argument("--no-corners", action="store_true", help="skip the corner-sum comparison leg")
+    ap.add_argument("--no-2d", action="store_true", help="skip the 2D (triangle) leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (--gpus must be 1)", file=sys.stderr)
@@ -563,6 +619,7 @@ def main() -> int:
     configs = None if args.no_configs else configs_leg(ctx, max(1, min(args.steps, 3)), 1, peaks,
                                                       refined=not args.no_refined)
     corners = None if args.no_corners else corner_leg(ctx, max(1, min(args.steps, 3)), 1)
+    tris = None if args.no_2d else tris_leg(ctx, max(1, min(args.steps, 3)), 1)
 
     traffic, traffic_src = clip_traffic()
     deposits_per_s = pieces / (clip_ms * 1e-3)
@@ -625,6 +682,7 @@ def main() -> int:
         "two_stage": amr,
         "configs": configs,
         "corner_sums": corners,
+        "triangles_2d": tris,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
