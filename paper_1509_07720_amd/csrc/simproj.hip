@@ -6,8 +6,9 @@
 //   k_fill      zero the output (unless SP_ACCUMULATE) and the per-call state
 //   k_setup     per simplex: gather, unwrap, cell coordinates, orientation;
 //               a simplex inside one cell deposits its whole mass at once
-//               (Appendix D, first step); the others are binned into cost
-//               classes, big ones split into groups of x-slabs
+//               (Appendix D, first step; merged per cell and block first);
+//               the others are binned into cost classes, big ones cut into
+//               work items of consecutive x-slabs sized by expected pieces
 //   k_scan      class offsets, most expensive class first
 //   k_scatter   the work items in class order
 //   k_clip      persistent waves pull 64 items at a time; each lane sweeps
@@ -15,6 +16,11 @@
 //               polytope held in LDS and depositing each piece
 //   k_clip(big) items whose polytope overflowed, resumed with more room
 //   k_finalize  hi+lo -> out, FP64 total mass
+// Other entry points: sp_vertex_density (k_vd_accum, k_vd_finish), the
+// accuracy-controlled projection (k_flag, k_tag, k_widen, k_gather_tagged,
+// k_patch), the two-stage projection (k_amr_level, k_amr_scatter, k_donor),
+// the corner-sum projection (k_corner) and the batched launch (the same
+// kernels over many problems, captured in a graph).
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdarg.h>
@@ -1260,8 +1266,10 @@ struct Prepared {
 
 // Scratch layout and descriptors for a launch over n problems.
 template <int D, typename T>
+// work_lists = false (the corner-sum path) leaves out the set-up, item and
+// overflow lists that only the clipping kernels use.
 static sp_status prepare(sp_ctx *ctx, const sp_problem *probs, int n, std::vector<Prepared<T>> &out, int64_t &ntotal,
-                         bool batched = false)
+                         bool batched = false, bool work_lists = true)
 {
     const bool fp32 = sizeof(T) == 4;
     ntotal = 0;
@@ -1276,16 +1284,16 @@ static sp_status prepare(sp_ctx *ctx, const sp_problem *probs, int n, std::vecto
     // room for the split items: half the simplices plus 2M (16 MB), enough
     // for ~1.3e8 pieces of big simplices at the default item size
     const unsigned extra_cap = (unsigned)(ntotal / 2 + (1 << 21));
-    const size_t nitems = (size_t)ntotal + extra_cap;
+    const size_t nitems = work_lists ? (size_t)ntotal + extra_cap : 0;
     size_t off = 0;
     const size_t o_tinfo = off;
-    off = align_up(off + sizeof(uint32_t) * (size_t)(ntotal > 0 ? ntotal : 1));
+    if (work_lists) off = align_up(off + sizeof(uint32_t) * (size_t)(ntotal > 0 ? ntotal : 1));
     const size_t o_items = off;
     off = align_up(off + sizeof(uint64_t) * nitems);
     const size_t o_iprob = off;
     if (batched) off = align_up(off + sizeof(uint16_t) * nitems);  // problem id per item
     const size_t o_ovf = off;
-    off = align_up(off + sizeof(Ovf) * OVF_CAP);
+    if (work_lists) off = align_up(off + sizeof(Ovf) * OVF_CAP);
     const size_t o_lo = off;
     off = align_up(off + sizeof(float) * lo_cells);
     sp_status st = ensure_scratch(ctx, off);
@@ -1324,12 +1332,12 @@ static sp_status prepare(sp_ctx *ctx, const sp_problem *probs, int n, std::vecto
                 loff += q.ncell;
             }
         }
-        p.tinfo = reinterpret_cast<uint32_t *>(base + o_tinfo) + toff;
+        p.tinfo = work_lists ? reinterpret_cast<uint32_t *>(base + o_tinfo) + toff : nullptr;
         toff += prob->n_simplex;
-        p.items = reinterpret_cast<uint64_t *>(base + o_items);
-        p.item_prob = batched ? reinterpret_cast<uint16_t *>(base + o_iprob) : nullptr;
+        p.items = work_lists ? reinterpret_cast<uint64_t *>(base + o_items) : nullptr;
+        p.item_prob = batched && work_lists ? reinterpret_cast<uint16_t *>(base + o_iprob) : nullptr;
         p.extra_cap = extra_cap;
-        p.ovf = reinterpret_cast<Ovf *>(base + o_ovf);
+        p.ovf = work_lists ? reinterpret_cast<Ovf *>(base + o_ovf) : nullptr;
         p.cs = ctx->cs;
         p.es = ctx->es;
         p.slab_group = ctx->tune.slab_group;
@@ -1449,7 +1457,7 @@ extern "C" sp_status sp_project_tets_corners(sp_ctx *ctx, const sp_problem *prob
     HIPCHECK(hipSetDevice(ctx->device));
     std::vector<Prepared<double>> v;
     int64_t ntotal = 0;
-    st = prepare<3, double>(ctx, prob, 1, v, ntotal);
+    st = prepare<3, double>(ctx, prob, 1, v, ntotal, false, false);
     if (st != SP_OK) return st;
     const Prepared<double> &q = v[0];
     hipLaunchKernelGGL(k_clear_state, dim3(1), dim3(64), 0, s, ctx->cs, q.total);
