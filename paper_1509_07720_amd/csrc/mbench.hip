@@ -7,7 +7,11 @@
 //   mbench copy   <MiB> [reps]   stream MiB of float4 from one buffer to another
 //   mbench atomic <MiB> [reps]   atomic adds to random cells of a MiB grid:
 //                                FP32 plain, FP32 returning + compensated (as the
-//                                FP32 deposit) and FP64 plain (as the FP64 deposit)
+//                                FP32 deposit), FP64 plain (as the FP64 deposit)
+//                                and 64-bit compare-and-swap
+//   mbench lds    [reps]         atomic adds to random words of a 16 KiB LDS
+//                                table per block, FP32 and FP64 (the set-up
+//                                kernel's per-cell merge uses the FP64 form)
 //
 // Each mode prints one JSON line per measurement.
 #include <hip/hip_runtime.h>
@@ -73,10 +77,66 @@ __global__ void k_atomic64(double *g, uint32_t n, int iters)
     }
 }
 
+__global__ void k_cas64(unsigned long long *g, uint32_t n, int iters)
+{
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    for (int i = 0; i < iters; ++i) {
+        const uint32_t a = mix(t * 131u + (uint32_t)i * 7919u) % n;
+        atomicCAS(g + a, (unsigned long long)i, (unsigned long long)t);
+    }
+}
+
+template <typename F>
+__global__ void k_lds(F *sink, int iters)
+{
+    constexpr int N = 16384 / sizeof(F);
+    __shared__ F tab[N];
+    for (int e = threadIdx.x; e < N; e += blockDim.x) tab[e] = F(0);
+    __syncthreads();
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    for (int i = 0; i < iters; ++i) atomicAdd(&tab[mix(t * 131u + (uint32_t)i * 7919u) % N], F(1));
+    __syncthreads();
+    if (threadIdx.x == 0) sink[blockIdx.x] = tab[0];
+}
+
 int main(int argc, char **argv)
 {
+    if (argc >= 2 && !strcmp(argv[1], "lds")) {
+        const int reps = argc > 2 ? atoi(argv[2]) : 5;
+        if (reps < 1 || reps > 1000) {
+            fprintf(stderr, "reps must be in 1..1000\n");
+            return 2;
+        }
+        hipDeviceProp_t prop;
+        CHECK(hipGetDeviceProperties(&prop, 0));
+        const int blocks = prop.multiProcessorCount * 8, iters = 1024;
+        double *sink = nullptr;
+        CHECK(hipMalloc(&sink, sizeof(double) * blocks));
+        hipEvent_t e0, e1;
+        CHECK(hipEventCreate(&e0));
+        CHECK(hipEventCreate(&e1));
+        const double ops = (double)blocks * 256 * iters;
+        for (int f64 = 0; f64 < 2; ++f64) {
+            for (int r = 0; r <= reps; ++r) {
+                CHECK(hipEventRecord(e0, 0));
+                if (f64)
+                    hipLaunchKernelGGL(k_lds<double>, dim3(blocks), dim3(256), 0, 0, sink, iters);
+                else
+                    hipLaunchKernelGGL(k_lds<float>, dim3(blocks), dim3(256), 0, 0, (float *)sink, iters);
+                CHECK(hipEventRecord(e1, 0));
+                CHECK(hipEventSynchronize(e1));
+                float ms = 0.f;
+                CHECK(hipEventElapsedTime(&ms, e0, e1));
+                if (r > 0)
+                    printf("{\"mode\": \"lds\", \"kind\": \"%s\", \"adds\": %.0f, \"ms\": %.4f, \"adds_per_s\": %.4e}\n",
+                           f64 ? "f64" : "f32", ops, ms, ops / (ms * 1e-3));
+            }
+        }
+        CHECK(hipFree(sink));
+        return 0;
+    }
     if (argc < 3) {
-        fprintf(stderr, "usage: %s copy|atomic MiB [reps]\n", argv[0]);
+        fprintf(stderr, "usage: %s copy|atomic MiB [reps] | lds [reps]\n", argv[0]);
         return 2;
     }
     const size_t mib = strtoull(argv[2], nullptr, 10);
@@ -121,11 +181,13 @@ int main(int argc, char **argv)
         const uint32_t n = (uint32_t)(bytes / sizeof(float));
         const int blocks = prop.multiProcessorCount * 32, iters = 64;
         const double ops = (double)blocks * 256 * iters;
-        const char *kinds[3] = {"plain", "returning+compensated", "f64"};
-        for (int comp = 0; comp < 3; ++comp) {
+        const char *kinds[4] = {"plain", "returning+compensated", "f64", "cas64"};
+        for (int comp = 0; comp < 4; ++comp) {
             for (int r = 0; r <= reps; ++r) {
                 CHECK(hipEventRecord(e0, 0));
-                if (comp == 2)  // the same cells as doubles: the first half of both buffers' bytes
+                if (comp == 3)  // 64-bit words over the same bytes
+                    hipLaunchKernelGGL(k_cas64, dim3(blocks), dim3(256), 0, 0, (unsigned long long *)hi, n / 2, iters);
+                else if (comp == 2)  // the same cells as doubles: the first half of both buffers' bytes
                     hipLaunchKernelGGL(k_atomic64, dim3(blocks), dim3(256), 0, 0, (double *)hi, n / 2, iters);
                 else if (comp)
                     hipLaunchKernelGGL(k_atomic<true>, dim3(blocks), dim3(256), 0, 0, hi, lo, n, iters);
