@@ -717,8 +717,9 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(clip_waves_p
 // and adds each vertex's terms to its cell(s).  Grid-stride over simplices.
 // The kernel waits on memory far more than it computes; held to 2 waves
 // per SIMD (128 VGPRs, the rest spilled) it ran 1.7x faster than at 1 wave
-// with 256 VGPRs, and 3 or 4 waves ran slower again.
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_corner(ProbDev<double> p)
+// with 256 VGPRs, and 3 or 4 waves ran slower again.  One-wave blocks
+// measured 7 % faster than 256-thread ones.
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_corner(ProbDev<double> p)
 {
     const int64_t st = (int64_t)gridDim.x * blockDim.x;
     for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < p.n; s += st) {
@@ -1464,7 +1465,7 @@ extern "C" sp_status sp_project_tets_corners(sp_ctx *ctx, const sp_problem *prob
     if (!q.accumulate)
         hipLaunchKernelGGL(k_fill<double>, dim3(grid_blocks(q.ncell, 256)), dim3(256), 0, s, q.p.out, q.ncell);
     if (ntotal > 0)
-        hipLaunchKernelGGL(k_corner, dim3(grid_blocks((size_t)ntotal, 256)), dim3(256), 0, s, q.p);
+        hipLaunchKernelGGL(k_corner, dim3(grid_blocks((size_t)ntotal, 64)), dim3(64), 0, s, q.p);
     if (q.total)
         hipLaunchKernelGGL(k_finalize<double>, dim3(grid_blocks(q.ncell, 256 * 8)), dim3(256), 0, s, q.p.out, nullptr,
                            0, q.ncell, q.to_mass, q.total);
