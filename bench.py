@@ -14,10 +14,11 @@ Also reported (not part of `value`): the per-vertex density estimate on the
 against plain FP32C and FP64, the two-stage (coarsened + donor-cell)
 projection against the exact one, the other 3D configurations with their
 roofline fractions, and the paper's corner-sum formulation against the
-clipping projection.  With --batch, the batched workload (64
-Zel'dovich meshes of 1e4..2e6 tets onto grids of 32^3..256^3) is also timed:
-one captured graph launch for all 64 problems against 64 sequential calls,
-in FP32C and FP64.
+clipping projection.  The batched workload (64 Zel'dovich meshes of
+1e4..2e6 tets onto grids of 32^3..256^3) is timed as one captured graph
+launch for all 64 problems, after the autotuner has picked its launch
+parameters, against 64 sequential calls, in FP32C and FP64 (--no-batch
+skips it).
 
 Prints one JSON line (see the "metric" field).  --gpus above 1 is refused:
 this build measures one GPU.
@@ -121,9 +122,13 @@ def atomic_peaks():
 
 def batch_leg(ctx, steps, warmup, peaks=None):
     """The batched workload: one graph launch for 64 problems against 64
-    sequential calls; FP32C and FP64.  With the pieces counted one problem
-    at a time (untimed), the batched launch's ALU, HBM and atomic fractions
-    as for the other workloads, over the whole launch."""
+    sequential calls; FP32C and FP64.  The launch parameters are tuned on the
+    64 problems first (sp_autotune with a cache file, timed separately).
+    With the pieces counted one problem at a time (untimed), the batched
+    launch's ALU, HBM and atomic fractions as for the other workloads, over
+    the whole launch."""
+    import tempfile
+
     import torch
 
     from paper_1509_07720_amd import simproj, synth
@@ -155,6 +160,16 @@ def batch_leg(ctx, steps, warmup, peaks=None):
             for r in recs:
                 simproj._check(simproj.sp_project_tets(ctx.handle, r, code, stream), "sp_project_tets")
 
+        saved = ctx.tuning()
+        cache = os.path.join(tempfile.mkdtemp(prefix="simproj-tune-"), "tune.txt")
+        t = time.perf_counter()
+        tuned = ctx.autotune(3, recs, precision=prec, cache_path=cache)
+        tune_s = time.perf_counter() - t
+        t = time.perf_counter()
+        ctx.autotune(3, recs, precision=prec, cache_path=cache)  # found in the cache: no timing
+        cached_s = time.perf_counter() - t
+        log(f"batch {prec}: autotuned slab group {tuned[0]}, blocks/CU {tuned[1]} in {tune_s:.1f}s "
+            f"(cache hit {cached_s * 1e3:.1f} ms)")
         pieces = 0
         ctx.profile(2)
         for r in recs:
@@ -169,7 +184,9 @@ def batch_leg(ctx, steps, warmup, peaks=None):
         batched()  # first call: capture and instantiation
         torch.cuda.synchronize()
         first = time.perf_counter() - t
-        row = {"first_call_ms": first * 1e3, "pieces": pieces}
+        row = {"first_call_ms": first * 1e3, "pieces": pieces,
+               "autotune": {"slab_group": tuned[0], "blocks_per_cu": tuned[1], "tune_s": tune_s,
+                            "cache_hit_s": cached_s}}
         for name, fn in (("batched", batched), ("sequential", sequential)):
             for _ in range(warmup):
                 fn()
@@ -186,6 +203,7 @@ def batch_leg(ctx, steps, warmup, peaks=None):
         row["batched"].update({"alu_frac": pieces * FLOPS_PER_PIECE / sec / 1e12 / peak_alu,
                                "hbm_frac": algo / sec / 1e9 / PEAK_HBM_GBS,
                                "atomic_frac": pieces / sec / apk if apk else None})
+        ctx.set_tuning(*saved)
         res[prec] = row
         log(f"batch {prec}: batched {row['batched']['ms_per_step']:.1f} ms, "
             f"sequential {row['sequential']['ms_per_step']:.1f} ms, first call {first * 1e3:.0f} ms")
@@ -535,7 +553,7 @@ def main() -> int:
     ap.add_argument("--cpu-sample", type=int, default=200_000, help="tets projected by the CPU oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--batch", action="store_true", help="also time the 64-problem batched workload")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-problem batched workload")
     ap.add_argument("--no-atomic-peak", action="store_true", help="skip the atomic-rate measurement (mbench)")
     ap.add_argument("--no-vertex-density", action="store_true", help="skip the per-vertex density leg")
     ap.add_argument("--no-accuracy", action="store_true", help="skip the accuracy-control leg")
@@ -612,7 +630,7 @@ def main() -> int:
         log(f"fp64: {sec64 * 1e3:.3f} ms/step, {n / sec64:.3e} tets/s, mass err {err64:.2e}")
         del xyz64, rho64, out64
 
-    batch = batch_leg(ctx, max(1, min(args.steps, 3)), 1, peaks) if args.batch else None
+    batch = None if args.no_batch else batch_leg(ctx, max(1, min(args.steps, 3)), 1, peaks)
     vdens = None if args.no_vertex_density else vertex_density_leg(ctx, max(1, args.steps), 1)
     accur = None if args.no_accuracy else accuracy_leg(ctx, max(1, min(args.steps, 5)), 1)
     amr = None if args.no_amr else amr_leg(ctx, max(1, min(args.steps, 5)), 1)

@@ -42,9 +42,10 @@
  * All projection calls are asynchronous: they validate their arguments on
  * the host, enqueue kernels and return.  On the device every simplex is
  * checked before it is cut: one with a vertex index outside [0, n_vert), a
- * non-finite position or density, or an extent of half the box or more on a
- * periodic axis (32768 cells on another) is skipped; with SP_VALIDATE the
- * first such error is reported by sp_sync_status.  The context owns its
+ * non-finite position or density, an extent of half the box or more on a
+ * periodic axis, or an extent of 32768 cells or more on any axis is skipped
+ * (SP_E_PERIODIC_SPAN for both extent limits); with SP_VALIDATE the first
+ * such error is reported by sp_sync_status.  The context owns its
  * scratch memory; a context must not be used by two host threads at once,
  * and calls on one context must be ordered (one stream, or synchronised).
  */
@@ -64,7 +65,8 @@ typedef enum {
     SP_E_INVALID_ARG = 1,   /* null pointer, bad dims/sizes, unsupported flag */
     SP_E_OUT_OF_RANGE = 2,  /* (SP_VALIDATE) a vertex index outside [0, n_vert) */
     SP_E_NONFINITE = 3,     /* (SP_VALIDATE) a NaN/Inf position or density */
-    SP_E_PERIODIC_SPAN = 4, /* (SP_VALIDATE) a simplex spans >= extent/2 on a periodic axis */
+    SP_E_PERIODIC_SPAN = 4, /* (SP_VALIDATE) a simplex spans >= extent/2 on a periodic axis,
+                               or 32768 cells or more on any axis */
     SP_E_NO_MEMORY = 5,     /* scratch allocation failed */
     SP_E_DEVICE = 6,        /* no usable HIP device, or a HIP call failed */
     SP_E_UNSUPPORTED = 7,   /* valid request this build does not handle */

@@ -466,7 +466,7 @@ __global__ __launch_bounds__(256) void k_setup(ProbDev<T> p0, Batch b)
                 const float per_slab = est_all / (float)sx;
                 const int G = (int)fminf((float)p.slab_group, fmaxf(1.0f, floorf(p.item_pieces / per_slab)));
                 nit = (sx + G - 1) / G;
-                if (nit > 4095) nit = 4095;  // 12-bit field of the item count
+                if (nit > MAX_ITEMS) nit = MAX_ITEMS;  // 12-bit field of the item count
             }
         } else if (p.validate && st == SETUP_BAD_INDEX) {
             record_error(p.es, SP_E_OUT_OF_RANGE);
@@ -493,7 +493,7 @@ __global__ __launch_bounds__(256) void k_setup(ProbDev<T> p0, Batch b)
             const float est = est_all / (float)nit;
             int cls = 1;
             while (cls < NCLS - 1 && (float)(1u << cls) < est) ++cls;
-            info = ((uint32_t)cls << 28) | ((uint32_t)nit << 16) | (uint32_t)sx;
+            info = pack_setup(cls, nit, sx);
             atomicAdd(&s_hist[cls], (unsigned)nit);
         }
         p.tinfo[s] = info;
@@ -548,7 +548,7 @@ __global__ __launch_bounds__(256) void k_scatter(ProbDev<T> p0, Batch b)
         const int64_t s = s0 + (int64_t)j * blockDim.x + threadIdx.x;
         info[j] = s < p.n ? p.tinfo[s] : 0u;
         local[j] = 0u;
-        if (info[j]) local[j] = atomicAdd(&s_cnt[info[j] >> 28], (info[j] >> 16) & 0xfffu);
+        if (info[j]) local[j] = atomicAdd(&s_cnt[setup_class(info[j])], (unsigned)setup_items(info[j]));
     }
     __syncthreads();
     if (threadIdx.x < NCLS && s_cnt[threadIdx.x])
@@ -558,14 +558,12 @@ __global__ __launch_bounds__(256) void k_scatter(ProbDev<T> p0, Batch b)
     for (int j = 0; j < IPT; ++j) {
         if (!info[j]) continue;
         const int64_t s = s0 + (int64_t)j * blockDim.x + threadIdx.x;
-        const int cls = (int)(info[j] >> 28), nit = (int)((info[j] >> 16) & 0xfffu), sx = (int)(info[j] & 0xffffu);
+        const int cls = setup_class(info[j]), nit = setup_items(info[j]), sx = setup_span(info[j]);
         const unsigned pos = s_base[cls] + local[j];
-        const int per = (sx + nit - 1) / nit;
         for (int k = 0; k < nit; ++k) {
-            int sb = k * per;
-            int sc = sx - sb < per ? sx - sb : per;
-            if (sc <= 0) sc = 0;
-            p0.items[pos + k] = (uint64_t)(uint32_t)s | ((uint64_t)sb << 32) | ((uint64_t)sc << 48);
+            int sb, sc;
+            item_range(sx, nit, k, sb, sc);
+            p0.items[pos + k] = pack_item((uint32_t)s, sb, sc);
             if (BATCH) p0.item_prob[pos + k] = (uint16_t)pi;
         }
     }
@@ -645,9 +643,9 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(clip_waves_p
                     pid = o.pid;
                 } else {
                     uint64_t item = p.items[it];
-                    sid = (int64_t)(uint32_t)item;
-                    sb = (int)((item >> 32) & 0xffffu);
-                    sc = (int)(item >> 48);
+                    sid = (int64_t)item_simplex(item);
+                    sb = item_first(item);
+                    sc = item_count(item);
                     pid = !SINGLE && b.nprob ? (int)p.item_prob[it] : 0;
                 }
                 const ProbDev<T> q = !SINGLE && b.nprob ? static_cast<const ProbDev<T> *>(b.probs)[pid] : p0;

@@ -24,9 +24,43 @@ struct GridDev {
     double out_scale;   // 1 for density output, cell volume for mass output
 };
 
-// Largest bounding-box extent, in cells, of one simplex on a non-periodic
-// axis (work items encode slab indices in 16 bits).
+// Largest bounding-box extent, in cells, of one simplex along any axis,
+// periodic or not: work items and the set-up record encode slab counts and
+// indices in 16 bits (a periodic axis also needs the extent below half the
+// box, checked separately).
 constexpr int MAX_SPAN = 32768;
+
+// Set-up record of one simplex for the binning kernels: cost class (4 bits),
+// number of work items (12 bits) and the span of its outermost sweep axis
+// (16 bits; MAX_SPAN keeps it below 2^15); 0 means no work items.  A work
+// item holds the simplex index (32 bits), its first slab and its slab count
+// (16 bits each).
+constexpr int MAX_ITEMS = 4095;
+
+SP_HD inline uint32_t pack_setup(int cls, int nit, int sx)
+{
+    return ((uint32_t)cls << 28) | ((uint32_t)nit << 16) | (uint32_t)sx;
+}
+SP_HD inline int setup_class(uint32_t r) { return (int)(r >> 28); }
+SP_HD inline int setup_items(uint32_t r) { return (int)((r >> 16) & 0xfffu); }
+SP_HD inline int setup_span(uint32_t r) { return (int)(r & 0xffffu); }
+
+SP_HD inline uint64_t pack_item(uint32_t s, int sb, int sc)
+{
+    return (uint64_t)s | ((uint64_t)(uint32_t)sb << 32) | ((uint64_t)(uint32_t)sc << 48);
+}
+SP_HD inline uint32_t item_simplex(uint64_t it) { return (uint32_t)it; }
+SP_HD inline int item_first(uint64_t it) { return (int)((it >> 32) & 0xffffu); }
+SP_HD inline int item_count(uint64_t it) { return (int)(it >> 48); }
+
+// The k-th of nit work items over sx slabs: first slab and slab count.
+SP_HD inline void item_range(int sx, int nit, int k, int &sb, int &sc)
+{
+    const int per = (sx + nit - 1) / nit;
+    sb = k * per;
+    sc = sx - sb < per ? sx - sb : per;
+    if (sc < 0) sc = 0;
+}
 
 enum SetupStatus : int {
     SETUP_OK = 0,
@@ -174,7 +208,7 @@ SP_HD inline int setup_f32(const float *xyz, int64_t n_vert, const int32_t *simp
             else L.v[a].z = l;
             lmax = l > lmax ? l : lmax;
         }
-        if (g.periodic[d] ? !(lmax < 0.5f * (float)g.dims[d]) : !(lmax < (float)MAX_SPAN)) return SETUP_BAD_SPAN;
+        if (!(lmax < (float)MAX_SPAN) || (g.periodic[d] && !(lmax < 0.5f * (float)g.dims[d]))) return SETUP_BAD_SPAN;
         L.anchor[d] = kmin;
         L.span[d] = (int)floorf(lmax) + 1;
     }
@@ -230,7 +264,7 @@ SP_HD inline int setup_f64(const double *xyz, int64_t n_vert, const int32_t *sim
             umin = (a == 0 || u[a] < umin) ? u[a] : umin;
             umax = (a == 0 || u[a] > umax) ? u[a] : umax;
         }
-        if (g.periodic[d] ? !((umax - umin) < 0.5 * (double)g.dims[d]) : !((umax - umin) < (double)MAX_SPAN - 1.0))
+        if (!((umax - umin) < (double)MAX_SPAN - 1.0) || (g.periodic[d] && !((umax - umin) < 0.5 * (double)g.dims[d])))
             return SETUP_BAD_SPAN;
         double kmin = floor(umin);
         for (int a = 0; a < K; ++a) {

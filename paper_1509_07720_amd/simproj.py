@@ -10,8 +10,10 @@ is no fallback path.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import sys
 from typing import Optional, Sequence
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -257,6 +259,12 @@ class Context:
             self.handle = None
 
     def __del__(self):
+        # At interpreter shutdown the module globals this needs may already
+        # be gone; the default contexts are closed by the atexit hook below
+        # while everything is still alive, and the process end releases the
+        # rest.
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -424,6 +432,17 @@ class Context:
 # module-level helpers on a per-device default context
 
 _DEFAULT = {}
+
+
+def _close_defaults() -> None:
+    """Close the default contexts at interpreter exit, before module teardown
+    (each close waits for its device and frees its memory)."""
+    while _DEFAULT:
+        _, ctx = _DEFAULT.popitem()
+        ctx.close()
+
+
+atexit.register(_close_defaults)
 
 
 def default_context(device: int = 0) -> Context:

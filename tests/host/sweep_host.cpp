@@ -121,3 +121,48 @@ extern "C" int sweep_host(const float *xyz, int64_t n_vert, const int32_t *simp,
     }
     return 0;
 }
+
+// Set-up status and outermost span of one triangle (corners in cell units)
+// on a periodic dims[0] x dims[1] grid over the unit box: the 2D case whose
+// x-span has to fit the 16-bit fields of the binning records.
+extern "C" int setup_tri_host(const float *corners, const int *dims, int *span_out)
+{
+    GridDev g;
+    memset(&g, 0, sizeof g);
+    for (int d = 0; d < 3; ++d) {
+        g.dims[d] = d < 2 ? dims[d] : 1;
+        g.periodic[d] = 1;
+        g.s_hi[d] = (float)g.dims[d];
+        g.scale[d] = g.dims[d];
+        g.extent[d] = 1.0;
+    }
+    float xyz[6];
+    for (int a = 0; a < 3; ++a)
+        for (int d = 0; d < 2; ++d) xyz[2 * a + d] = corners[2 * a + d] / (float)dims[d];
+    const int32_t simp[3] = {0, 1, 2};
+    const float rho[3] = {1.f, 1.f, 1.f};
+    Local<float> L;
+    const int st = setup_f32<2>(xyz, 3, simp, 0, rho, false, g, true, L);
+    span_out[0] = L.span[0];
+    span_out[1] = L.span[1];
+    return st;
+}
+
+// Round trip of the binning records for a simplex of outer span sx cut into
+// nit work items: 0 when the set-up record decodes to (cls, nit, sx) and the
+// items, decoded, cover slabs [0, sx) once each in order; else a code.
+extern "C" int pack_roundtrip_host(int cls, int nit, int sx, uint32_t simplex)
+{
+    const uint32_t r = pack_setup(cls, nit, sx);
+    if (setup_class(r) != cls || setup_items(r) != nit || setup_span(r) != sx) return 1;
+    int next = 0;
+    for (int k = 0; k < nit; ++k) {
+        int sb, sc;
+        item_range(sx, nit, k, sb, sc);
+        const uint64_t it = pack_item(simplex, sb, sc);
+        if (item_simplex(it) != simplex || item_first(it) != sb || item_count(it) != sc) return 2;
+        if (sc > 0 && sb != next) return 3;
+        next = sc > 0 ? sb + sc : next;
+    }
+    return next == sx ? 0 : 4;
+}

@@ -238,3 +238,55 @@ def test_autotune_picks_candidate_and_caches(ctx, tmp_path):
         _assert_parity(d.grid(), _ref(prob, prec), prec, "after autotune")
     finally:
         ctx.set_tuning(*old)
+
+
+def _span_skips(ctx):
+    """(status, simplices skipped for their span) reported since the last
+    sp_sync_status."""
+    import re
+
+    st = ctx.sync_status()
+    if st == simproj.SP_OK:
+        return st, 0
+    m = re.search(r"(\d+) periodic span", simproj.sp_last_error())
+    return st, int(m.group(1)) if m else -1
+
+
+def test_full_batch_recipe(ctx):
+    """The batched workload at full size, in the launch form the benchmark
+    times (64 Zel'dovich meshes of 1e4..2e6 tets onto grids of 32^3..256^3,
+    FP32C, one batched launch), with no problem left out.  Every problem of
+    the batch equals its own single sp_project_tets call cell by cell; the
+    every-16th-tet subsets of all 64 problems, projected as one batch, match
+    the oracle problem by problem (projection is additive over simplices),
+    and the simplices skipped for spanning half the box are the same number
+    on both sides."""
+    prec = "fp32c"
+    probs = [synth.as_float32(p) for p in synth.batch_3d()]
+    print("full batch:", len(probs), "problems,", sum(p["simplices"].shape[0] for p in probs), "tets", flush=True)
+    devs = [Dev(p, prec) for p in probs]
+    ctx.project_batch([d.rec for d in devs], precision=prec)
+    st_full, skip_full = _span_skips(ctx)
+    assert st_full in (simproj.SP_OK, simproj.SP_E_PERIODIC_SPAN), simproj.sp_last_error()
+    code = simproj.SP_PREC_FP32C
+    for i, (p, d) in enumerate(zip(probs, devs)):
+        single = Dev(p, prec)
+        assert simproj.sp_project_tets(ctx.handle, single.rec, code, simproj._stream_ptr(None)) == simproj.SP_OK
+        a, b = d.out.double(), single.out.double()
+        scale = max(float(b.abs().max()), 1e-300)
+        assert float((a - b).abs().max()) <= 1e-5 * scale, i
+        assert abs(float(d.total.cpu()[0]) - float(single.total.cpu()[0])) <= 1e-7 * abs(float(single.total.cpu()[0]))
+        del single
+    ctx.sync_status()
+    del devs
+    torch.cuda.empty_cache()
+    subs = [synth.subset(p, 16) for p in probs]
+    sdevs = [Dev(p, prec) for p in subs]
+    ctx.project_batch([d.rec for d in sdevs], precision=prec)
+    st_sub, skip_sub = _span_skips(ctx)
+    oracle_skips = 0
+    for i, (p, d) in enumerate(zip(subs, sdevs)):
+        ref = oracle.project(p)
+        oracle_skips += ref["stats"]["n_bad_span"]
+        _assert_parity(d.grid(), ref, prec, f"subset of problem {i}")
+    assert skip_sub == oracle_skips, (st_sub, skip_sub, oracle_skips)

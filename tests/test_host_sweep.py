@@ -94,3 +94,26 @@ def test_non_periodic_box_with_flat_simplices(lib):
     p = folded(synth.zeldovich_3d(n=16, grid=32, sigma_cells=1.0, seed=8))
     st = check(lib, p)
     assert st[0] > 0  # the exactly flat ones are skipped by both sides
+
+
+def test_2d_outer_span_fits_the_binning_records(lib):
+    """A triangle's x-span is the slab count of its binning record (16 bits).
+    On a periodic axis of 2^18 cells a triangle may span far more than that
+    while staying under half the box; the set-up must refuse every span of
+    32768 cells or more (reported as a span error) and accept smaller ones,
+    whose records and work items round-trip exactly."""
+    V = ctypes.c_void_p
+    lib.setup_tri_host.argtypes = [V, V, V]
+    lib.pack_roundtrip_host.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint32]
+    dims = np.array([1 << 18, 64], dtype=np.int32)
+    span = np.zeros(2, dtype=np.int32)
+    SETUP_OK, SETUP_BAD_SPAN = 0, 4
+    for width, ok in ((70000.5, False), (65536.25, False), (32768.5, False), (32766.5, True), (1000.5, True)):
+        tri = np.array([3.25, 1.5, 3.25 + width, 2.5, 3.25 + width / 2, 9.75], dtype=np.float32)
+        st = lib.setup_tri_host(tri.ctypes.data, dims.ctypes.data, span.ctypes.data)
+        assert st == (SETUP_OK if ok else SETUP_BAD_SPAN), (width, st)
+        if ok:
+            sx = int(span[0])
+            assert sx == int(np.floor(3.25 + width)) - 3 + 1
+            for nit in (1, 2, 7, min(4095, sx)):
+                assert lib.pack_roundtrip_host(15, nit, sx, 0xFFFFFFFF) == 0, (sx, nit)

@@ -129,6 +129,42 @@ def test_p5_exact_rational_agreement(dim):
     assert float(tot) == pytest.approx(float(np.sum(vol * R.mean(axis=1))), rel=1e-14)
 
 
+@pytest.mark.parametrize("dim", [2, 3])
+def test_p5_coverage_scale_recomputed_exactly(dim):
+    """The coverage scale C_j (the denominator of every per-cell error bound)
+    recomputed independently: for every simplex, every cell of its bounding
+    box whose exact rational piece has positive volume takes max_a |rho_a|;
+    C_j is the largest such value times the cell volume.  Signed densities,
+    so that the largest |rho| and not the largest rho counts; the oracle must
+    match exactly, neither inflated nor missing a cell.  Corners are odd
+    multiples of 1/128 (general position: no corner on a grid plane), since
+    a simplex that only touches a cell along its boundary has a zero-volume
+    piece that rounding in the FP64 oracle may count as positive."""
+    rng = np.random.default_rng(17 + dim)
+    dims = [16] * dim
+    n = 12 if dim == 3 else 40
+    X = (2 * rng.integers(128, 416, (n, dim + 1, dim)) + 1) / 128.0
+    R = np.round(rng.uniform(-1.5, 1.5, (n, dim + 1)) * 16) / 16  # signed
+    prob = _single(dim, X, R.ravel(), dims, per_corner=True)
+    res = oracle.project(prob, nthreads=2)
+    cov = res["cov"] * np.prod(dims)
+    want = np.zeros_like(cov)
+    piece = exact.piece3 if dim == 3 else exact.piece2
+    for Xs, Rs in zip(X.tolist(), R.tolist()):
+        pts = [tuple(Fr(v) for v in x) + (Fr(r),) for x, r in zip(Xs, Rs)]
+        lo = [int(np.floor(min(p[d] for p in pts))) for d in range(dim)]
+        hi = [int(np.floor(max(p[d] for p in pts))) for d in range(dim)]
+        rmax = max(abs(r) for r in Rs)
+        for c in np.ndindex(*[h - l + 1 for l, h in zip(lo, hi)]):
+            cell = tuple(l + k for l, k in zip(lo, c))
+            vol, _ = piece(pts, cell)
+            if vol > 0:
+                idx = tuple(reversed([cell[d] % dims[d] for d in range(dim)]))
+                want[idx] = max(want[idx], rmax)
+    assert np.count_nonzero(want) > 20
+    assert np.array_equal(cov, want)
+
+
 # ---------------------------------------------------------------- P6 Franklin
 
 def test_p6_franklin_corner_sum_on_pieces():
