@@ -124,6 +124,23 @@ void sp_destroy(sp_ctx *ctx);
  * enqueue nothing. */
 sp_status sp_project_tets(sp_ctx *ctx, const sp_problem *prob, sp_precision prec, void *stream);
 
+/* sp_project_tets for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same operation, arguments, results and errors, but the
+ * call allocates nothing -- no hipMalloc, hipFree or allocating library
+ * routine, and no HIP events (stage profiling does not record it).  Its work
+ * lists live in a static scratch array of 128 MiB in device memory, one copy
+ * per GPU the library runs on, held from the first sp_create on that device
+ * until the process ends.  A problem whose work lists do not fit returns
+ * SP_E_NO_MEMORY synchronously and enqueues nothing; roughly, 16 bytes per
+ * simplex plus, when out_lo is NULL in FP32C mode, 4 bytes per cell, on top
+ * of 26 MiB of fixed lists (about 6M tetrahedra with a caller-held out_lo).
+ * Every call on one GPU shares that GPU's array, and a call leaves its
+ * contents behind: each call writes everything it reads before reading it,
+ * but calls whose work overlaps in time on one GPU (different streams or
+ * contexts, unsynchronised) race on it and must not be issued. */
+sp_status sp_project_tets_noalloc(sp_ctx *ctx, const sp_problem *prob, sp_precision prec, void *stream);
+
 /* Project triangles (D = 2): the same operation in two dimensions (the
  * paper's 2D, i.e. 4D phase-space, case; Section 3.1 eq. eq:E02D). */
 sp_status sp_project_tris(sp_ctx *ctx, const sp_problem *prob, sp_precision prec, void *stream);
@@ -150,21 +167,29 @@ sp_status sp_project_tris(sp_ctx *ctx, const sp_problem *prob, sp_precision prec
 sp_status sp_project_tets_accurate(sp_ctx *ctx, const sp_problem *prob, int accurate_bits, int wrong_bits,
                                    int64_t *counts, void *stream);
 
-/* Two-stage projection of tetrahedra onto a coarsened-then-gathered grid
- * (Section 4, "Calculation of the acceleration": exact projection onto an
- * adaptive grid whose cells are no larger than the smallest simplex height
- * they meet, then donor cell onto the uniform grid).  Read per simplex here:
- * a tetrahedron whose smallest height (3 V / largest face area, in cells of
- * this grid, after the minimum-image unwrap, in FP64) is h is projected
- * exactly onto the grid coarsened 2^l times per axis, l = floor(log2 h)
- * clamped to [0, max_level]; every coarse cell's mass is then spread evenly
- * over the 8^l cells it covers and the levels are summed.  Large simplices
- * thus cost pieces at their own resolution; the result is the exact
- * projection only where every simplex has level 0 (max_level 0 is
- * sp_project_tets).
- *   prob          as for sp_project_tets (SP_ACCUMULATE rejected)
+/* Projection of tetrahedra onto an adaptive grid, gathered onto the uniform
+ * grid by donor cell (Section 4, "Calculation of the acceleration").  The
+ * adaptive grid is an octree over the caller's grid, refined region by
+ * region as long as its cells are larger than the smallest height of any
+ * tetrahedron intersecting them, down to the caller's cells at most: a block
+ * of side 2^l cells stays whole only if every tetrahedron meeting its
+ * interior has smallest height h >= 2^l (h = 3 V / largest face area, in
+ * cells, after the minimum-image unwrap, FP64; "meeting" decided by a
+ * separating axis test in FP64).  The density is projected exactly onto the
+ * leaves, and each leaf's mass is spread evenly over the cells it holds.
+ * The result is the exact projection wherever the leaves are single cells
+ * (around thin simplices) and a block average elsewhere (inside large ones).
+ * Each tetrahedron is projected at the coarsest level at which no block of
+ * its bounding box is refined, so large simplices away from thin ones cost
+ * pieces at their own resolution.
+ *   prob          as for sp_project_tets (SP_ACCUMULATE rejected; a given
+ *                 out_lo is zeroed, out holds the whole result)
  *   max_level     0..10; every dims[d] must be a multiple of 2^max_level
- *   level_counts  optional HOST int64[max_level + 1]: simplices per level
+ *                 (max_level 0 is sp_project_tets)
+ *   level_counts  optional HOST int64[max_level + 1]: simplices projected at
+ *                 each level
+ * A tetrahedron whose bounding box holds more than 2^22 blocks of the size
+ * it is tested against marks them all without the test (a finer grid there).
  * Synchronises with `stream` once (to size the levels); the levels are
  * projected in one batched launch (sp_project_batch). */
 sp_status sp_project_tets_amr(sp_ctx *ctx, const sp_problem *prob, sp_precision prec, int max_level,

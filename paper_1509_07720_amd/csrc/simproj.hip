@@ -18,7 +18,8 @@
 //   k_finalize  hi+lo -> out, FP64 total mass
 // Other entry points: sp_vertex_density (k_vd_accum, k_vd_finish), the
 // accuracy-controlled projection (k_flag, k_tag, k_widen, k_gather_tagged,
-// k_patch), the two-stage projection (k_amr_level, k_amr_scatter, k_donor),
+// k_patch), the adaptive-grid projection (k_amr_level, k_amr_mark, k_amr_refine,
+// k_amr_plevel, k_amr_scatter, k_amr_restrict, k_amr_gather),
 // the corner-sum projection (k_corner) and the batched launch (the same
 // kernels over many problems, captured in a graph).
 #include <hip/hip_runtime.h>
@@ -30,6 +31,7 @@
 #include <string.h>
 
 #include <chrono>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -43,6 +45,15 @@ namespace {
 
 constexpr int WG = 64;       // lanes per block in the clip kernels (one wave)
 constexpr int NCLS = 16;     // cost classes
+// Precision route of FP32C problems: a simplex whose bounding box spans
+// WIDE_SPAN cells or more along some axis is clipped and integrated in FP64
+// (its pieces deposited compensated into the FP32 grids).  Positions local
+// to a simplex carry a rounding of half an ulp of its span (R12's u * span),
+// and at 64 cells that is 3.8e-6 of a cell, the most the per-cell bound of
+// 1e-5 leaves room for.  Such simplices get the class CLS_WIDE, which no
+// other simplex uses; their work items come first in the list.
+constexpr int WIDE_SPAN = 64;
+constexpr int CLS_WIDE = NCLS - 1;
 // Polytope vertex slots per lane.  FP32: 17 slots (17 KB of LDS per wave)
 // let 9 waves share a CU when the kernel keeps to 168 VGPRs (3 waves per
 // SIMD); the rare polytope that needs more is finished by the 32-slot
@@ -60,6 +71,7 @@ struct CallState {
     unsigned cursor[NCLS];
     unsigned total;
     unsigned head;
+    unsigned head_wide;
     unsigned extra;
     unsigned ovf_count;
     unsigned ovf_head;
@@ -123,6 +135,15 @@ struct DepF32 {
     float scale;
     int suppress_iy, suppress_iz, suppress_ix;  // resume: skip pieces before this one
     int count;
+
+    // a piece computed in FP64 (a simplex routed to FP64)
+    __device__ void operator()(int ix, int iy, int iz, double v)
+    {
+        if (ix == suppress_ix && (iy < suppress_iy || (iy == suppress_iy && iz < suppress_iz))) return;
+        ++count;
+        size_t idx;
+        if (cell(ix, iy, iz, idx)) add(idx, v);
+    }
 
     __device__ void operator()(int ix, int iy, int iz, float v)
     {
@@ -300,6 +321,12 @@ __device__ inline int setup_any(const ProbDev<double> &p, int64_t s, bool valida
 {
     return setup_f64<D>(p.xyz, p.n_vert, p.simp, s, p.rho, p.per_corner != 0, p.g, validate, L);
 }
+// a simplex of an FP32C problem routed to FP64 (float inputs, double set-up)
+template <int D>
+__device__ inline int setup_any(const ProbDev<float> &p, int64_t s, bool validate, Local<double> &L)
+{
+    return setup_f64<D, float>(p.xyz, p.n_vert, p.simp, s, p.rho, p.per_corner != 0, p.g, validate, L);
+}
 
 constexpr SweepOrder kIdentity = {{0, 1, 2}};
 
@@ -309,11 +336,11 @@ __device__ inline int wrap_index(int k, int n)
     return k < 0 ? k + n : k;
 }
 
-// Deposit for a simplex swept in order o (L already relabelled by o).
-template <typename T>
-__device__ inline typename DepFor<T>::type make_dep(const ProbDev<T> &p, const Local<T> &L, const SweepOrder &o);
-template <>
-__device__ inline DepF32 make_dep<float>(const ProbDev<float> &p, const Local<float> &L, const SweepOrder &o)
+// Deposit for a simplex swept in order o (L already relabelled by o); the
+// grid type follows the problem, whatever precision the simplex is clipped
+// in (TL).
+template <typename TL>
+__device__ inline DepF32 make_dep(const ProbDev<float> &p, const Local<TL> &L, const SweepOrder &o)
 {
     DepF32 d;
     d.hi = p.out;
@@ -333,8 +360,8 @@ __device__ inline DepF32 make_dep<float>(const ProbDev<float> &p, const Local<fl
     d.count = 0;
     return d;
 }
-template <>
-__device__ inline DepF64 make_dep<double>(const ProbDev<double> &p, const Local<double> &L, const SweepOrder &o)
+template <typename TL>
+__device__ inline DepF64 make_dep(const ProbDev<double> &p, const Local<TL> &L, const SweepOrder &o)
 {
     DepF64 d;
     d.out = p.out;
@@ -432,6 +459,7 @@ __global__ __launch_bounds__(256) void k_setup(ProbDev<T> p0, Batch b)
         s = s0 + threadIdx.x;
     }
     int nit = 0, sx = 0;  // nit > 0: work items wanted for the clip kernel
+    bool wide = false;    // FP32C simplex routed to FP64
     float est_all = 0.0f;
     if (s < p.n) {
         Local<T> L;
@@ -458,15 +486,31 @@ __global__ __launch_bounds__(256) void k_setup(ProbDev<T> p0, Batch b)
                 if (p.count_pieces) atomicAdd(&p.cs->pieces, 1ull);
             } else {
                 const int a0 = sweep_order(L).ax[0];
+                wide = sizeof(T) == 4 && max(L.span[0], max(L.span[1], L.span[2])) >= WIDE_SPAN;
                 sx = D == 3 ? sel3(L.span[0], L.span[1], L.span[2], a0) : L.span[0];
+                if constexpr (sizeof(T) == 4) {
+                    if (wide) {
+                        // the items of a simplex routed to FP64 count the slabs
+                        // of the FP64 set-up, which the clip will repeat
+                        Local<double> Lw;
+                        if (setup_any<D>(p, s, false, Lw) == SETUP_OK) {
+                            const int aw = sweep_order(Lw).ax[0];
+                            sx = D == 3 ? sel3(Lw.span[0], Lw.span[1], Lw.span[2], aw) : Lw.span[0];
+                        } else {
+                            sx = 0;  // the FP64 set-up drops it (zero volume, span): no items
+                        }
+                    }
+                }
                 // work items of about item_pieces expected pieces and at
                 // most slab_group slabs: small simplices stay whole, big
                 // ones are spread over many lanes
                 est_all = piece_estimate<T, D>(L);
-                const float per_slab = est_all / (float)sx;
-                const int G = (int)fminf((float)p.slab_group, fmaxf(1.0f, floorf(p.item_pieces / per_slab)));
-                nit = (sx + G - 1) / G;
-                if (nit > MAX_ITEMS) nit = MAX_ITEMS;  // 12-bit field of the item count
+                if (sx > 0) {
+                    const float per_slab = est_all / (float)sx;
+                    const int G = (int)fminf((float)p.slab_group, fmaxf(1.0f, floorf(p.item_pieces / per_slab)));
+                    nit = (sx + G - 1) / G;
+                    if (nit > MAX_ITEMS) nit = MAX_ITEMS;  // 12-bit field of the item count
+                }
             }
         } else if (p.validate && st == SETUP_BAD_INDEX) {
             record_error(p.es, SP_E_OUT_OF_RANGE);
@@ -492,7 +536,8 @@ __global__ __launch_bounds__(256) void k_setup(ProbDev<T> p0, Batch b)
             if (nit > 1 && s_extra_base + my_extra + (unsigned)(nit - 1) > p.extra_cap) nit = 1;
             const float est = est_all / (float)nit;
             int cls = 1;
-            while (cls < NCLS - 1 && (float)(1u << cls) < est) ++cls;
+            while (cls < CLS_WIDE - 1 && (float)(1u << cls) < est) ++cls;
+            if (wide) cls = CLS_WIDE;
             info = pack_setup(cls, nit, sx);
             atomicAdd(&s_hist[cls], (unsigned)nit);
         }
@@ -519,6 +564,8 @@ __global__ void k_scan(CallState *cs)
             off += cs->hist[c];
         }
         cs->total = off;
+        // the wide class comes first; the FP32 clip kernel starts after it
+        cs->head = cs->hist[CLS_WIDE];
     }
 }
 
@@ -583,17 +630,23 @@ __global__ __launch_bounds__(256) void k_scatter(ProbDev<T> p0, Batch b)
 template <int D, typename T, int MAXV>
 constexpr int clip_waves_per_simd() { return D == 3 && sizeof(T) == 4 && MAXV <= 17 ? 3 : 1; }
 
-template <int D, typename T, int MAXV, bool SINGLE>
+// T is the arithmetic of the clip, TI that of the problem (inputs and
+// grids).  TI = float with T = double is the FP64 route of an FP32C problem:
+// it takes the CLS_WIDE items at the head of the list, and a polytope that
+// outgrows its slots there is an internal error (it runs with 32 slots).
+template <int D, typename T, int MAXV, bool SINGLE, typename TI = T>
 __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(clip_waves_per_simd<D, T, MAXV>()))) void k_clip(
-    ProbDev<T> p0, Batch b, int overflow_pass)
+    ProbDev<TI> p0, Batch b, int overflow_pass)
 {
     static_assert(WG == 64, "the queue logic assumes one wave per block");
-    const ProbDev<T> &p = p0;  // fields shared by every problem of the launch
+    constexpr bool WIDE = sizeof(T) == 8 && sizeof(TI) == 4;
+    const ProbDev<TI> &p = p0;  // fields shared by every problem of the launch
     constexpr int SLOTS = D == 3 ? MAXV : 2 * MAXP2;
     __shared__ V4<T> s_p[SLOTS][WG];  // 3D: polytope slots (S4, same size); 2D: polygon buffers
     const int lane = threadIdx.x;
-    const unsigned total = overflow_pass ? min(p.cs->ovf_count, (unsigned)OVF_CAP) : p.cs->total;
-    unsigned *head = overflow_pass ? &p.cs->ovf_head : &p.cs->head;
+    const unsigned total = overflow_pass ? min(p.cs->ovf_count, (unsigned)OVF_CAP)
+                                         : (WIDE ? p.cs->hist[CLS_WIDE] : p.cs->total);
+    unsigned *head = overflow_pass ? &p.cs->ovf_head : (WIDE ? &p.cs->head_wide : &p.cs->head);
     // the few resumed items of the overflow pass are spread over many waves
     const unsigned chunk = overflow_pass ? 8u : (unsigned)WG;
     unsigned q_base = 0u, q_n = 0u, q_h = 0u;  // current chunk [q_base, q_base + q_n), next unclaimed q_h
@@ -607,7 +660,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(clip_waves_p
     P2.n = 0;
     bool busy = false;
     Local<T> L;
-    typename DepFor<T>::type dep;
+    typename DepFor<TI>::type dep;
     Sweep3 S;
     int64_t sid = 0;
     int sb = 0, sc = 0, pid = 0;
@@ -648,7 +701,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(clip_waves_p
                     sc = item_count(item);
                     pid = !SINGLE && b.nprob ? (int)p.item_prob[it] : 0;
                 }
-                const ProbDev<T> q = !SINGLE && b.nprob ? static_cast<const ProbDev<T> *>(b.probs)[pid] : p0;
+                const ProbDev<TI> q = !SINGLE && b.nprob ? static_cast<const ProbDev<TI> *>(b.probs)[pid] : p0;
                 Local<T> L0;
                 if (setup_any<D>(q, sid, false, L0) == SETUP_OK) {
                     const SweepOrder ord = D == 3 ? sweep_order(L0) : kIdentity;
@@ -685,7 +738,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(clip_waves_p
         busy = false;
         if (p.count_pieces && dep.count) atomicAdd(&p.cs->pieces, (unsigned long long)dep.count);  // counting runs only
         if (r < 0) {
-            if (!overflow_pass) {
+            if (!overflow_pass && !WIDE) {
                 unsigned k = atomicAdd(&p.cs->ovf_count, 1u);
                 if (k < OVF_CAP) {
                     Ovf o;
@@ -891,14 +944,114 @@ __global__ __launch_bounds__(256) void k_patch(float *hi, float *lo, const uint8
     }
 }
 
-// Two-stage projection (Section 4, "Calculation of the acceleration"): each
-// tetrahedron is projected exactly onto the grid coarsened 2^l times per
-// axis, l = floor(log2 h) clamped to [0, max_level], h its smallest height
-// (3 V / largest face area) in fine-cell units after the minimum-image
-// unwrap, all in FP64; the coarse grids are then spread onto the fine grid
-// by donor cell.
+// Adaptive-grid projection (Section 4, "Calculation of the acceleration"):
+// an octree over the grid is refined region by region while its cells are
+// larger than the smallest height of any simplex intersecting them (or down
+// to the grid's own cells), the density is projected exactly onto it, and
+// each leaf's mass is spread evenly over the grid cells it holds (donor
+// cell).  Kernels, in order:
+//   k_amr_level    the level l_i = floor(log2 h_i) of every tetrahedron
+//                  (clamped to [0, max_level]; h_i its smallest height,
+//                  3 V / largest face area, in cells, FP64)
+//   k_amr_mark     every block of side 2^(l_i + 1) a tetrahedron intersects
+//                  is marked (separating axis test in FP64)
+//   k_amr_refine   a block is refined if it or a block inside it is marked
+//   k_amr_plevel   the level each tetrahedron is projected at: the largest
+//                  level <= l_i at which no block of its bounding box is
+//                  refined, so that every leaf it meets is a union of its
+//                  cells there
+//   (compaction by level, one batched exact projection, in mass units)
+//   k_amr_restrict the leaf sums, level by level: a block's mass is its own
+//                  level's projection plus the sums of its 8 children
+//   k_amr_gather   each grid cell takes its leaf's mass / 8^level
+
+// Unwrapped corner positions in cells of the grid, FP64: on periodic axes the
+// minimum image of the first corner, then (x - origin) * scale.
 template <typename T>
-__global__ __launch_bounds__(256) void k_amr_level(ProbDev<T> p, int max_level, uint8_t *level, unsigned *counts)
+__device__ inline bool amr_corners(const ProbDev<T> &p, int64_t s, double P[4][3])
+{
+    int32_t vi[4];
+    for (int a = 0; a < 4; ++a) {
+        vi[a] = p.simp[s * 4 + a];
+        if (vi[a] < 0 || vi[a] >= p.n_vert) return false;
+    }
+    for (int d = 0; d < 3; ++d) {
+        const double x0 = (double)p.xyz[(int64_t)vi[0] * 3 + d];
+        for (int a = 0; a < 4; ++a) {
+            double x = (double)p.xyz[(int64_t)vi[a] * 3 + d];
+            if (!isfinite(x)) return false;
+            if (p.g.periodic[d]) x = x - p.g.extent[d] * rint((x - x0) / p.g.extent[d]);
+            P[a][d] = (x - p.g.origin[d]) * p.g.scale[d];
+        }
+    }
+    return true;
+}
+
+// Interiors of the tetrahedron P and the box lo + [0, size]^3 intersect:
+// separating axis test over the 3 axes, the 4 face normals and the 18 edge x
+// axis products, strict on every non-zero axis.  Evaluated without fused
+// multiply-adds, in the order written (the same FP64 steps decide the same
+// way on any implementation that takes them).
+__device__ inline bool amr_meets(const double n[25][3], const double P[4][3], const double lo[3], double size)
+{
+#pragma clang fp contract(off)
+    double rel[4][3];
+    for (int a = 0; a < 4; ++a)
+        for (int d = 0; d < 3; ++d) rel[a][d] = P[a][d] - lo[d];
+    for (int k = 0; k < 25; ++k) {
+        const double nx = n[k][0], ny = n[k][1], nz = n[k][2];
+        if (nx == 0.0 && ny == 0.0 && nz == 0.0) continue;
+        double tmin = 0.0, tmax = 0.0;
+        for (int a = 0; a < 4; ++a) {
+            const double t = (nx * rel[a][0] + ny * rel[a][1]) + nz * rel[a][2];
+            tmin = a == 0 || t < tmin ? t : tmin;
+            tmax = a == 0 || t > tmax ? t : tmax;
+        }
+        const double sx = nx * size, sy = ny * size, sz = nz * size;
+        const double bmin = (fmin(0.0, sx) + fmin(0.0, sy)) + fmin(0.0, sz);
+        const double bmax = (fmax(0.0, sx) + fmax(0.0, sy)) + fmax(0.0, sz);
+        if (!(tmin < bmax && bmin < tmax)) return false;
+    }
+    return true;
+}
+
+__device__ inline void amr_axes(const double P[4][3], double n[25][3])
+{
+#pragma clang fp contract(off)
+    n[0][0] = 1.0, n[0][1] = 0.0, n[0][2] = 0.0;
+    n[1][0] = 0.0, n[1][1] = 1.0, n[1][2] = 0.0;
+    n[2][0] = 0.0, n[2][1] = 0.0, n[2][2] = 1.0;
+    const int F[4][3] = {{1, 2, 3}, {0, 2, 3}, {0, 1, 3}, {0, 1, 2}};
+    for (int f = 0; f < 4; ++f) {
+        double e1[3], e2[3];
+        for (int d = 0; d < 3; ++d) {
+            e1[d] = P[F[f][1]][d] - P[F[f][0]][d];
+            e2[d] = P[F[f][2]][d] - P[F[f][0]][d];
+        }
+        n[3 + f][0] = e1[1] * e2[2] - e1[2] * e2[1];
+        n[3 + f][1] = e1[2] * e2[0] - e1[0] * e2[2];
+        n[3 + f][2] = e1[0] * e2[1] - e1[1] * e2[0];
+    }
+    const int E[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+    for (int k = 0; k < 6; ++k) {
+        double e[3];
+        for (int d = 0; d < 3; ++d) e[d] = P[E[k][1]][d] - P[E[k][0]][d];
+        double *a = n[7 + 3 * k];
+        a[0] = 0.0, a[1] = e[2], a[2] = -e[1];
+        a[3] = -e[2], a[4] = 0.0, a[5] = e[0];
+        a[6] = e[1], a[7] = -e[0], a[8] = 0.0;
+    }
+}
+
+// Blocks of side 2^l of a grid with dims: their counts per axis and the
+// offset of level l's byte grid in a buffer holding levels 1..max_level.
+struct AmrLevels {
+    int nb[11][3];
+    size_t off[11];
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_amr_level(ProbDev<T> p, int max_level, uint8_t *level)
 {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= p.n) return;
@@ -942,7 +1095,124 @@ __global__ __launch_bounds__(256) void k_amr_level(ProbDev<T> p, int max_level, 
         }
     }
     level[s] = (uint8_t)lv;
-    atomicAdd(&counts[lv], 1u);
+}
+
+// Blocks of side 2^(l_i + 1) the tetrahedron intersects are marked (byte
+// stores of 1; concurrent ones agree).  Tetrahedra at max_level mark nothing.
+template <typename T>
+__global__ __launch_bounds__(64) void k_amr_mark(ProbDev<T> p, int max_level, const uint8_t *level, uint8_t *marks,
+                                                 AmrLevels L)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= p.n) return;
+    const int l = (int)level[s] + 1;
+    if (l > max_level) return;
+    double P[4][3];
+    if (!amr_corners(p, s, P)) return;
+    double n[25][3];
+    amr_axes(P, n);
+    const double size = (double)(1 << l);
+    int blo[3], bhi[3];
+    for (int d = 0; d < 3; ++d) {
+        double mn = P[0][d], mx = P[0][d];
+        for (int a = 1; a < 4; ++a) {
+            mn = fmin(mn, P[a][d]);
+            mx = fmax(mx, P[a][d]);
+        }
+        blo[d] = (int)floor(mn / size);
+        bhi[d] = (int)floor(mx / size);
+    }
+    const int *nb = L.nb[l];
+    uint8_t *m = marks + L.off[l];
+    // a bounding box of more than 2^22 blocks is marked whole without the
+    // test (a finer grid there than the rule asks for; it keeps one thread's
+    // loop bounded)
+    const bool all = (double)(bhi[0] - blo[0] + 1) * (bhi[1] - blo[1] + 1) * (bhi[2] - blo[2] + 1) > 4194304.0;
+    for (int bz = blo[2]; bz <= bhi[2]; ++bz) {
+        int wz = bz;
+        if (p.g.periodic[2]) wz = wrap_index(bz, nb[2]);
+        else if (bz < 0 || bz >= nb[2]) continue;
+        for (int by = blo[1]; by <= bhi[1]; ++by) {
+            int wy = by;
+            if (p.g.periodic[1]) wy = wrap_index(by, nb[1]);
+            else if (by < 0 || by >= nb[1]) continue;
+            for (int bx = blo[0]; bx <= bhi[0]; ++bx) {
+                int wx = bx;
+                if (p.g.periodic[0]) wx = wrap_index(bx, nb[0]);
+                else if (bx < 0 || bx >= nb[0]) continue;
+                const double lo[3] = {bx * size, by * size, bz * size};
+                if (all || amr_meets(n, P, lo, size)) m[((size_t)wz * nb[1] + wy) * nb[0] + wx] = 1;
+            }
+        }
+    }
+}
+
+// Level l's marks become "refined": marked, or a child (level l - 1) refined.
+__global__ __launch_bounds__(256) void k_amr_refine(uint8_t *marks, AmrLevels L, int l)
+{
+    const int *nb = L.nb[l], *nc = L.nb[l - 1];
+    const size_t nblk = (size_t)nb[0] * nb[1] * nb[2];
+    uint8_t *m = marks + L.off[l];
+    const uint8_t *c = marks + L.off[l - 1];
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nblk; i += (size_t)gridDim.x * blockDim.x) {
+        const int x = (int)(i % nb[0]), y = (int)((i / nb[0]) % nb[1]), z = (int)(i / ((size_t)nb[0] * nb[1]));
+        uint8_t r = m[i];
+        for (int k = 0; k < 8 && !r; ++k) {
+            const int cx = 2 * x + (k & 1), cy = 2 * y + ((k >> 1) & 1), cz = 2 * z + (k >> 2);
+            r = c[((size_t)cz * nc[1] + cy) * nc[0] + cx];
+        }
+        m[i] = r;
+    }
+}
+
+// The projection level of each tetrahedron (and the count per level).
+template <typename T>
+__global__ __launch_bounds__(64) void k_amr_plevel(ProbDev<T> p, uint8_t *level, const uint8_t *refined, AmrLevels L,
+                                                   unsigned *counts)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= p.n) return;
+    int l = level[s];
+    double P[4][3];
+    if (l > 0 && amr_corners(p, s, P)) {
+        double mn[3], mx[3];
+        for (int d = 0; d < 3; ++d) {
+            mn[d] = mx[d] = P[0][d];
+            for (int a = 1; a < 4; ++a) {
+                mn[d] = fmin(mn[d], P[a][d]);
+                mx[d] = fmax(mx[d], P[a][d]);
+            }
+        }
+        for (; l > 0; --l) {
+            const double size = (double)(1 << l);
+            const int *nb = L.nb[l];
+            const uint8_t *r = refined + L.off[l];
+            // (a box of more than 2^22 blocks counts as refined: one level down)
+            bool any = (floor(mx[0] / size) - floor(mn[0] / size) + 1) * (floor(mx[1] / size) - floor(mn[1] / size) + 1) *
+                           (floor(mx[2] / size) - floor(mn[2] / size) + 1) > 4194304.0;
+            for (int bz = (int)floor(mn[2] / size); bz <= (int)floor(mx[2] / size) && !any; ++bz) {
+                int wz = bz;
+                if (p.g.periodic[2]) wz = wrap_index(bz, nb[2]);
+                else if (bz < 0 || bz >= nb[2]) continue;
+                for (int by = (int)floor(mn[1] / size); by <= (int)floor(mx[1] / size) && !any; ++by) {
+                    int wy = by;
+                    if (p.g.periodic[1]) wy = wrap_index(by, nb[1]);
+                    else if (by < 0 || by >= nb[1]) continue;
+                    for (int bx = (int)floor(mn[0] / size); bx <= (int)floor(mx[0] / size) && !any; ++bx) {
+                        int wx = bx;
+                        if (p.g.periodic[0]) wx = wrap_index(bx, nb[0]);
+                        else if (bx < 0 || bx >= nb[0]) continue;
+                        any = r[((size_t)wz * nb[1] + wy) * nb[0] + wx] != 0;
+                    }
+                }
+            }
+            if (!any) break;
+        }
+    } else {
+        l = 0;
+    }
+    level[s] = (uint8_t)l;
+    atomicAdd(&counts[l], 1u);
 }
 
 template <typename T>
@@ -959,15 +1229,48 @@ __global__ __launch_bounds__(256) void k_amr_scatter(ProbDev<T> p, const uint8_t
     }
 }
 
+// Level l's grid (masses of its own simplices) plus the sums of the 8
+// children of each of its cells in level l - 1's summed grid.
 template <typename T>
-__global__ __launch_bounds__(256) void k_donor(T *out, const T *coarse, int lv, int nx, int ny, size_t ncell, T factor)
+__global__ __launch_bounds__(256) void k_amr_restrict(T *up, const T *down, AmrLevels L, int l)
 {
-    const int cnx = nx >> lv, cny = ny >> lv;
+    const int *nb = L.nb[l], *nc = L.nb[l - 1];
+    const size_t nblk = (size_t)nb[0] * nb[1] * nb[2];
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nblk; i += (size_t)gridDim.x * blockDim.x) {
+        const int x = (int)(i % nb[0]), y = (int)((i / nb[0]) % nb[1]), z = (int)(i / ((size_t)nb[0] * nb[1]));
+        T acc = up[i];
+        for (int k = 0; k < 8; ++k) {
+            const int cx = 2 * x + (k & 1), cy = 2 * y + ((k >> 1) & 1), cz = 2 * z + (k >> 2);
+            acc += down[((size_t)cz * nc[1] + cy) * nc[0] + cx];
+        }
+        up[i] = acc;
+    }
+}
+
+// Each grid cell: descend from the largest blocks while refined; the leaf's
+// summed mass / 8^level, divided by the cell volume for density output.
+// sums[l] points at level l's summed grid (sums[0] is out itself).
+struct AmrSums {
+    void *p[11];
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_amr_gather(T *out, AmrSums sums, const uint8_t *refined, AmrLevels L,
+                                                    int max_level, double to_out)
+{
+    const int *n0 = L.nb[0];
+    const size_t ncell = (size_t)n0[0] * n0[1] * n0[2];
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < ncell; i += (size_t)gridDim.x * blockDim.x) {
-        const size_t x = i % (size_t)nx, yz = i / (size_t)nx;
-        const size_t y = yz % (size_t)ny, z = yz / (size_t)ny;
-        const size_t c = ((z >> lv) * (size_t)cny + (y >> lv)) * (size_t)cnx + (x >> lv);
-        out[i] += coarse[c] * factor;
+        const int x = (int)(i % n0[0]), y = (int)((i / n0[0]) % n0[1]), z = (int)(i / ((size_t)n0[0] * n0[1]));
+        int l = max_level;
+        for (; l > 0; --l) {
+            const int *nb = L.nb[l];
+            if (!refined[L.off[l] + ((size_t)(z >> l) * nb[1] + (y >> l)) * nb[0] + (x >> l)]) break;
+        }
+        const int *nb = L.nb[l];
+        const T *a = static_cast<const T *>(sums.p[l]);
+        const T m = a[((size_t)(z >> l) * nb[1] + (y >> l)) * nb[0] + (x >> l)];
+        out[i] = (T)((double)m * (to_out / (double)(1ull << (3 * l))));
     }
 }
 
@@ -1006,8 +1309,20 @@ __global__ __launch_bounds__(256) void k_finalize(T *out, float *lo, int keep_lo
 
 enum Stage { ST_FILL, ST_SETUP, ST_BIN, ST_CLIP, ST_RETRY, ST_FINAL, ST_N };
 
+// Scratch of sp_project_tets_noalloc: a fixed array in device memory, one
+// copy per GPU the library runs on, held until the process ends.  In host
+// code `scratch` only names the symbol; its device address (per device) comes
+// from hipGetSymbolAddress, taken once per device by sp_create with that
+// device current, and only that address is ever handed to kernels.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)128 << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static void *g_noalloc_ptr[NOALLOC_MAX_DEVICES];
+static std::mutex g_noalloc_mu;
+
 struct sp_ctx {
     int device;
+    void *noalloc;   // this device's copy of `scratch` (NULL if its address could not be taken)
     int num_cu;
     void *scratch;
     size_t scratch_cap;
@@ -1128,6 +1443,16 @@ extern "C" sp_status sp_create(int hip_device, sp_ctx **ctx)
     c->profiling = 0;
     c->prof_calls = 0;
     c->last_clip_blocks = 0;
+    c->noalloc = nullptr;
+    if (hip_device < NOALLOC_MAX_DEVICES) {
+        std::lock_guard<std::mutex> lock(g_noalloc_mu);
+        if (!g_noalloc_ptr[hip_device]) {
+            void *ptr = nullptr;
+            if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) == hipSuccess) g_noalloc_ptr[hip_device] = ptr;
+            else (void)hipGetLastError();
+        }
+        c->noalloc = g_noalloc_ptr[hip_device];
+    }
     if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
         (void)hipFree(st);
         delete c;
@@ -1267,8 +1592,11 @@ struct Prepared {
 template <int D, typename T>
 // work_lists = false (the corner-sum path) leaves out the set-up, item and
 // overflow lists that only the clipping kernels use.
-static sp_status prepare(sp_ctx *ctx, const sp_problem *probs, int n, std::vector<Prepared<T>> &out, int64_t &ntotal,
-                         bool batched = false, bool work_lists = true)
+// fixed != NULL (the no-allocation entry point): lay the scratch out in
+// that buffer of fixed_cap bytes instead of the context's, with room for
+// fewer split items, and fail when it does not fit.
+static sp_status prepare(sp_ctx *ctx, const sp_problem *probs, int n, Prepared<T> *out, int64_t &ntotal,
+                         bool batched = false, bool work_lists = true, void *fixed = nullptr, size_t fixed_cap = 0)
 {
     const bool fp32 = sizeof(T) == 4;
     ntotal = 0;
@@ -1282,7 +1610,7 @@ static sp_status prepare(sp_ctx *ctx, const sp_problem *probs, int n, std::vecto
     if (ntotal >= ((int64_t)1 << 31)) return fail(SP_E_INVALID_ARG, "%lld simplices in one launch (limit 2^31)", (long long)ntotal);
     // room for the split items: half the simplices plus 2M (16 MB), enough
     // for ~1.3e8 pieces of big simplices at the default item size
-    const unsigned extra_cap = (unsigned)(ntotal / 2 + (1 << 21));
+    const unsigned extra_cap = (unsigned)(ntotal / 2 + (fixed ? (1 << 18) : (1 << 21)));
     const size_t nitems = work_lists ? (size_t)ntotal + extra_cap : 0;
     size_t off = 0;
     const size_t o_tinfo = off;
@@ -1295,10 +1623,17 @@ static sp_status prepare(sp_ctx *ctx, const sp_problem *probs, int n, std::vecto
     if (work_lists) off = align_up(off + sizeof(Ovf) * OVF_CAP);
     const size_t o_lo = off;
     off = align_up(off + sizeof(float) * lo_cells);
-    sp_status st = ensure_scratch(ctx, off);
-    if (st != SP_OK) return st;
-    char *base = reinterpret_cast<char *>(ctx->scratch);
-    out.resize(n);
+    char *base;
+    if (fixed) {
+        if (off > fixed_cap)
+            return fail(SP_E_NO_MEMORY, "the problem needs %zu bytes of scratch; the static scratch of the no-allocation "
+                                        "entry point holds %zu", off, fixed_cap);
+        base = reinterpret_cast<char *>(fixed);
+    } else {
+        sp_status st = ensure_scratch(ctx, off);
+        if (st != SP_OK) return st;
+        base = reinterpret_cast<char *>(ctx->scratch);
+    }
     int64_t toff = 0;
     size_t loff = 0;
     for (int i = 0; i < n; ++i) {
@@ -1351,7 +1686,7 @@ static sp_status prepare(sp_ctx *ctx, const sp_problem *probs, int n, std::vecto
 // bracketed by HIP events (profiling of direct calls; captured graphs are
 // timed as a whole).
 template <int D, typename T>
-static void enqueue(sp_ctx *ctx, const std::vector<Prepared<T>> &v, const Batch &b, int64_t nblocks, hipStream_t stream,
+static void enqueue(sp_ctx *ctx, const Prepared<T> *v, int nv, const Batch &b, int64_t nblocks, hipStream_t stream,
                     bool timers)
 {
     const bool fp32 = sizeof(T) == 4;
@@ -1361,7 +1696,8 @@ static void enqueue(sp_ctx *ctx, const std::vector<Prepared<T>> &v, const Batch 
     {
         StageTimer t = timer(ST_FILL);
         hipLaunchKernelGGL(k_clear_state, dim3(1), dim3(64), 0, stream, ctx->cs, single ? v[0].total : nullptr);
-        for (const Prepared<T> &q : v) {
+        for (int qi = 0; qi < nv; ++qi) {
+            const Prepared<T> &q = v[qi];
             if (!single && q.total) hipLaunchKernelGGL(k_fill<double>, dim3(1), dim3(64), 0, stream, q.total, (size_t)1);
             if (!q.accumulate)
                 hipLaunchKernelGGL(k_fill<T>, dim3(grid_blocks(q.ncell, 256)), dim3(256), 0, stream, q.p.out, q.ncell);
@@ -1405,11 +1741,20 @@ static void enqueue(sp_ctx *ctx, const std::vector<Prepared<T>> &v, const Batch 
             int rocc = 0;
             (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&rocc, kretry, WG, 0);
             hipLaunchKernelGGL(kretry, dim3(ctx->num_cu * (rocc < 1 ? 1 : rocc)), dim3(WG), 0, stream, p0, b, 1);
+            if constexpr (sizeof(T) == 4) {
+                // the simplices routed to FP64 (none in most launches: then
+                // every wave stops at its first claim)
+                auto kwide = k_clip<D, double, MAXV3_BIG, false, float>;
+                int wocc = 0;
+                (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&wocc, kwide, WG, 0);
+                hipLaunchKernelGGL(kwide, dim3(ctx->num_cu * (wocc < 1 ? 1 : wocc)), dim3(WG), 0, stream, p0, b, 0);
+            }
         }
     }
     {
         StageTimer t = timer(ST_FINAL);
-        for (const Prepared<T> &q : v) {
+        for (int qi = 0; qi < nv; ++qi) {
+            const Prepared<T> &q = v[qi];
             if (fp32 || q.total)
                 hipLaunchKernelGGL(k_finalize<T>, dim3(grid_blocks(q.ncell, 256 * 8)), dim3(256), 0, stream, q.p.out,
                                    q.p.lo, q.keep_lo ? 1 : 0, q.ncell, q.to_mass, q.total);
@@ -1423,13 +1768,14 @@ static sp_status project_impl(sp_ctx *ctx, const sp_problem *prob, hipStream_t s
     HIPCHECK(hipSetDevice(ctx->device));
     std::vector<Prepared<T>> v;
     int64_t ntotal = 0;
-    sp_status st = prepare<D, T>(ctx, prob, 1, v, ntotal);
+    v.resize(1);
+    sp_status st = prepare<D, T>(ctx, prob, 1, v.data(), ntotal);
     if (st != SP_OK) return st;
     Batch b = {nullptr, nullptr, 0};
     if (ctx->profiling) ctx->prof_calls++;
     {
         StageTimer whole(ctx->profiling ? ctx : nullptr, stream, &ctx->ev_call);
-        enqueue<D, T>(ctx, v, b, (ntotal + 255) / 256, stream, ctx->profiling != 0);
+        enqueue<D, T>(ctx, v.data(), (int)v.size(), b, (ntotal + 255) / 256, stream, ctx->profiling != 0);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(SP_E_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
@@ -1445,6 +1791,34 @@ extern "C" sp_status sp_project_tets(sp_ctx *ctx, const sp_problem *prob, sp_pre
     return prec == SP_PREC_FP32C ? project_impl<3, float>(ctx, prob, s) : project_impl<3, double>(ctx, prob, s);
 }
 
+// sp_project_tets without allocating: the work lists live in this device's
+// copy of the static scratch; stage timing is off (no events are created).
+extern "C" sp_status sp_project_tets_noalloc(sp_ctx *ctx, const sp_problem *prob, sp_precision prec, void *stream)
+{
+    sp_status st = check_problem(prob, 3, prec);
+    if (st != SP_OK) return st;
+    if (!ctx) return fail(SP_E_INVALID_ARG, "ctx is NULL");
+    if (!ctx->noalloc) return fail(SP_E_DEVICE, "the static scratch of device %d has no device address", ctx->device);
+    HIPCHECK(hipSetDevice(ctx->device));
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    Batch b = {nullptr, nullptr, 0};
+    int64_t ntotal = 0;
+    if (prec == SP_PREC_FP32C) {
+        Prepared<float> one;
+        st = prepare<3, float>(ctx, prob, 1, &one, ntotal, false, true, ctx->noalloc, NOALLOC_SCRATCH_BYTES);
+        if (st != SP_OK) return st;
+        enqueue<3, float>(ctx, &one, 1, b, (ntotal + 255) / 256, s, false);
+    } else {
+        Prepared<double> one;
+        st = prepare<3, double>(ctx, prob, 1, &one, ntotal, false, true, ctx->noalloc, NOALLOC_SCRATCH_BYTES);
+        if (st != SP_OK) return st;
+        enqueue<3, double>(ctx, &one, 1, b, (ntotal + 255) / 256, s, false);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(SP_E_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+    return SP_OK;
+}
+
 // Projection by corner sums (FP64): the same result as sp_project_tets in
 // FP64 mode, by the paper's own formulation, for comparison.
 extern "C" sp_status sp_project_tets_corners(sp_ctx *ctx, const sp_problem *prob, void *stream)
@@ -1456,7 +1830,8 @@ extern "C" sp_status sp_project_tets_corners(sp_ctx *ctx, const sp_problem *prob
     HIPCHECK(hipSetDevice(ctx->device));
     std::vector<Prepared<double>> v;
     int64_t ntotal = 0;
-    st = prepare<3, double>(ctx, prob, 1, v, ntotal, false, false);
+    v.resize(1);
+    st = prepare<3, double>(ctx, prob, 1, v.data(), ntotal, false, false);
     if (st != SP_OK) return st;
     const Prepared<double> &q = v[0];
     hipLaunchKernelGGL(k_clear_state, dim3(1), dim3(64), 0, s, ctx->cs, q.total);
@@ -1531,13 +1906,14 @@ extern "C" sp_status sp_project_tets_accurate(sp_ctx *ctx, const sp_problem *pro
     p1.total_mass = nullptr;
     std::vector<Prepared<float>> v;
     int64_t ntotal = 0;
-    st = prepare<3, float>(ctx, &p1, 1, v, ntotal);
+    v.resize(1);
+    st = prepare<3, float>(ctx, &p1, 1, v.data(), ntotal);
     if (st != SP_OK) return st;
     v[0].p.cmax = cmax;
     hipLaunchKernelGGL(k_fill<uint32_t>, dim3(grid_blocks(ncell, 256)), dim3(256), 0, s, cmax, ncell);
     hipLaunchKernelGGL(k_fill<unsigned long long>, dim3(1), dim3(64), 0, s, cnt, (size_t)2);
     Batch nb = {nullptr, nullptr, 0};
-    enqueue<3, float>(ctx, v, nb, (ntotal + 255) / 256, s, false);
+    enqueue<3, float>(ctx, v.data(), (int)v.size(), nb, (ntotal + 255) / 256, s, false);
     // 2. flags and tags
     const float factor = ldexpf(1.0f, wrong_bits + accurate_bits - 23);
     hipLaunchKernelGGL(k_flag, dim3(grid_blocks(ncell, 256)), dim3(256), 0, s, (const float *)prob->out,
@@ -1604,10 +1980,25 @@ static sp_status amr_impl(sp_ctx *ctx, const sp_problem *prob, sp_precision prec
     HIPCHECK(hipSetDevice(ctx->device));
     const int64_t n = prob->n_simplex;
     const bool per_corner = (prob->grid.flags & SP_RHO_PER_CORNER) != 0;
-    size_t ncell = 1;
-    for (int d = 0; d < 3; ++d) ncell *= (size_t)prob->grid.dims[d];
+    // block counts per level; byte grids of marks (later: refined) for
+    // levels 1..max_level, packed in one buffer
+    AmrLevels L;
+    memset(&L, 0, sizeof L);
+    size_t mark_bytes = 0;
+    size_t nblk[11];
+    for (int l = 0; l <= max_level; ++l) {
+        nblk[l] = 1;
+        for (int d = 0; d < 3; ++d) {
+            L.nb[l][d] = prob->grid.dims[d] >> l;
+            nblk[l] *= (size_t)L.nb[l][d];
+        }
+        if (l >= 1) {
+            L.off[l] = mark_bytes;
+            mark_bytes = align_up(mark_bytes + nblk[l]);
+        }
+    }
     // buffers: levels, counters, bases, compacted simplices (and corner
-    // densities), one coarse grid per level >= 1
+    // densities), marks, one summed grid per level >= 1
     size_t off = 0;
     const size_t o_lv = off;
     off = align_up(off + (size_t)(n > 0 ? n : 1));
@@ -1617,10 +2008,12 @@ static sp_status amr_impl(sp_ctx *ctx, const sp_problem *prob, sp_precision prec
     off = align_up(off + sizeof(int32_t) * 4 * (size_t)(n > 0 ? n : 1));
     const size_t o_rho = off;
     off = align_up(off + (per_corner ? sizeof(T) * 4 * (size_t)n : 0));
-    size_t o_coarse[16] = {0};
+    const size_t o_marks = off;
+    off = align_up(off + (mark_bytes > 0 ? mark_bytes : 1));
+    size_t o_sum[11] = {0};
     for (int l = 1; l <= max_level; ++l) {
-        o_coarse[l] = off;
-        off = align_up(off + sizeof(T) * (ncell >> (3 * l)));
+        o_sum[l] = off;
+        off = align_up(off + sizeof(T) * nblk[l]);
     }
     sp_status st = ensure_buf(ctx->aux[1], off);
     if (st != SP_OK) return st;
@@ -1631,52 +2024,70 @@ static sp_status amr_impl(sp_ctx *ctx, const sp_problem *prob, sp_precision prec
     unsigned *bases = counts + 32;
     int32_t *simp = reinterpret_cast<int32_t *>(base + o_simp);
     T *rho = per_corner ? reinterpret_cast<T *>(base + o_rho) : nullptr;
+    uint8_t *marks = reinterpret_cast<uint8_t *>(base + o_marks);
     std::vector<Prepared<T>> v;
     int64_t ntot = 0;
     // a descriptor of the input, for the per-simplex kernels
-    st = prepare<3, T>(ctx, prob, 1, v, ntot);
+    v.resize(1);
+    st = prepare<3, T>(ctx, prob, 1, v.data(), ntot);
     if (st != SP_OK) return st;
     const ProbDev<T> pin = v[0].p;
     unsigned hc[16] = {0}, hb[16] = {0};
     hipLaunchKernelGGL(k_fill<unsigned>, dim3(1), dim3(64), 0, s, counts, (size_t)48);
+    if (mark_bytes > 0)
+        hipLaunchKernelGGL(k_fill<uint8_t>, dim3(grid_blocks(mark_bytes, 256)), dim3(256), 0, s, marks, mark_bytes);
     if (n > 0) {
-        hipLaunchKernelGGL(k_amr_level<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, pin, max_level, lv, counts);
+        const unsigned nb64 = (unsigned)((n + 63) / 64), nb256 = (unsigned)((n + 255) / 256);
+        hipLaunchKernelGGL(k_amr_level<T>, dim3(nb256), dim3(256), 0, s, pin, max_level, lv);
+        if (max_level >= 1) {
+            hipLaunchKernelGGL(k_amr_mark<T>, dim3(nb64), dim3(64), 0, s, pin, max_level, (const uint8_t *)lv, marks, L);
+            for (int l = 2; l <= max_level; ++l)
+                hipLaunchKernelGGL(k_amr_refine, dim3(grid_blocks(nblk[l], 256)), dim3(256), 0, s, marks, L, l);
+        }
+        hipLaunchKernelGGL(k_amr_plevel<T>, dim3(nb64), dim3(64), 0, s, pin, lv, (const uint8_t *)marks, L, counts);
         HIPCHECK(hipMemcpyAsync(hc, counts, sizeof hc, hipMemcpyDeviceToHost, s));
         HIPCHECK(hipStreamSynchronize(s));
         for (int l = 1; l <= max_level; ++l) hb[l] = hb[l - 1] + hc[l - 1];
         HIPCHECK(hipMemcpyAsync(bases, hb, sizeof hb, hipMemcpyHostToDevice, s));
-        hipLaunchKernelGGL(k_amr_scatter<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, pin,
-                           (const uint8_t *)lv, cursor, (const unsigned *)bases, simp, rho);
+        hipLaunchKernelGGL(k_amr_scatter<T>, dim3(nb256), dim3(256), 0, s, pin, (const uint8_t *)lv, cursor,
+                           (const unsigned *)bases, simp, rho);
         HIPCHECK(hipStreamSynchronize(s));  // bases[] is read from host memory above
     }
-    // one problem per level (level 0 writes the caller's grid), projected in
-    // one batched launch; all levels add to the caller's total
+    // one problem per projection level, in mass units (level 0 writes the
+    // caller's grid), projected in one batched launch; all levels add to the
+    // caller's total; an unused level's grid is zeroed
     std::vector<sp_problem> probs;
-    std::vector<int> plev;
+    AmrSums sums;
+    memset(&sums, 0, sizeof sums);
+    sums.p[0] = prob->out;
     for (int l = 0; l <= max_level; ++l) {
-        if (l > 0 && hc[l] == 0) continue;
+        if (l > 0) sums.p[l] = base + o_sum[l];
+        if (l > 0 && hc[l] == 0) {
+            hipLaunchKernelGGL(k_fill<T>, dim3(grid_blocks(nblk[l], 256)), dim3(256), 0, s, (T *)sums.p[l], nblk[l]);
+            continue;
+        }
         sp_problem q = *prob;
         q.simplices = simp + 4 * (size_t)hb[l];
         q.n_simplex = hc[l];
         if (per_corner) q.rho = rho + 4 * (size_t)hb[l];
         for (int d = 0; d < 3; ++d) q.grid.dims[d] = prob->grid.dims[d] >> l;
-        if (l > 0) {
-            q.out = base + o_coarse[l];
-            q.out_lo = nullptr;
-        }
+        q.grid.flags |= SP_OUT_MASS;
+        q.out = sums.p[l];
+        q.out_lo = nullptr;
         probs.push_back(q);
-        plev.push_back(l);
     }
     st = batch_impl<3, T>(ctx, probs.data(), (int)probs.size(), prec, s);
     if (st != SP_OK) return st;
-    const bool mass = (prob->grid.flags & SP_OUT_MASS) != 0;
-    for (size_t k = 0; k < probs.size(); ++k) {
-        const int l = plev[k];
-        if (l == 0) continue;
-        const T factor = mass ? (T)(1.0 / (double)(1ull << (3 * l))) : T(1);
-        hipLaunchKernelGGL(k_donor<T>, dim3(grid_blocks(ncell, 256)), dim3(256), 0, s, (T *)prob->out,
-                           (const T *)probs[k].out, l, prob->grid.dims[0], prob->grid.dims[1], ncell, factor);
-    }
+    for (int l = 1; l <= max_level; ++l)
+        hipLaunchKernelGGL(k_amr_restrict<T>, dim3(grid_blocks(nblk[l], 256)), dim3(256), 0, s, (T *)sums.p[l],
+                           (const T *)sums.p[l - 1], L, l);
+    double cellvol = 1.0;
+    for (int d = 0; d < 3; ++d) cellvol *= prob->grid.extent[d] / (double)prob->grid.dims[d];
+    const double to_out = (prob->grid.flags & SP_OUT_MASS) ? 1.0 : 1.0 / cellvol;
+    hipLaunchKernelGGL(k_amr_gather<T>, dim3(grid_blocks(nblk[0], 256)), dim3(256), 0, s, (T *)prob->out, sums,
+                       (const uint8_t *)marks, L, max_level, to_out);
+    if (prob->out_lo)  // the whole result is in out
+        hipLaunchKernelGGL(k_fill<float>, dim3(grid_blocks(nblk[0], 256)), dim3(256), 0, s, prob->out_lo, nblk[0]);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(SP_E_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
     if (level_counts)
@@ -1717,7 +2128,8 @@ static sp_status batch_impl(sp_ctx *ctx, const sp_problem *probs, int n, sp_prec
     HIPCHECK(hipSetDevice(ctx->device));
     std::vector<Prepared<T>> v;
     int64_t ntotal = 0;
-    sp_status st = prepare<D, T>(ctx, probs, n, v, ntotal, true);
+    v.resize(n);
+    sp_status st = prepare<D, T>(ctx, probs, n, v.data(), ntotal, true);
     if (st != SP_OK) return st;
     uint64_t key = 1469598103934665603ull;
     const int dim = D;
@@ -1756,7 +2168,7 @@ static sp_status batch_impl(sp_ctx *ctx, const sp_problem *probs, int n, sp_prec
         // capture the whole launch sequence once; replays cost one launch
         hipGraph_t graph = nullptr;
         HIPCHECK(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
-        enqueue<D, T>(ctx, v, b, boffs[n], ctx->cap_stream, false);
+        enqueue<D, T>(ctx, v.data(), (int)v.size(), b, boffs[n], ctx->cap_stream, false);
         hipError_t e1 = hipStreamEndCapture(ctx->cap_stream, &graph);
         if (e1 != hipSuccess) {
             (void)hipFree(g.dev);

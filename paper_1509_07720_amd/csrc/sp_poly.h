@@ -266,6 +266,36 @@ struct Poly3 {
         live = 0xfu;
     }
 
+    // The tetrahedron translated by (-dx, -dy, 0), with the density's origin
+    // moved along (the gradient does not change): the sweep builds every
+    // column in a frame local to it.
+    SP_HD void init_tet_at(const V4<T> *v, T dx, T dy)
+    {
+        V4<T> w[4];
+        for (int i = 0; i < 4; ++i) {
+            w[i] = v[i];
+            w[i].x -= dx;
+            w[i].y -= dy;
+        }
+        init_tet(w);
+        o[0] = w[0].x;
+        o[1] = w[0].y;
+        o[2] = w[0].z;
+    }
+
+    // Move the frame by d along ax: every slot (used or not) and the
+    // density's origin.  Exact for whole cells when no coordinate changes
+    // sign, as for a column shifted down to its lowest cell.
+    SP_HD void shift(int ax, T d)
+    {
+#pragma unroll
+        for (int v = 0; v < MAXV; ++v) {
+            T *q = reinterpret_cast<T *>(&p[v * STRIDE]);
+            q[ax] -= d;
+        }
+        o[ax] -= d;
+    }
+
     // Every slot is read (unused slots hold stale but readable values) so
     // that the loads issue back to back instead of one per loop trip; the
     // result is masked by `live`.

@@ -233,9 +233,11 @@ SP_HD inline int setup_f32(const float *xyz, int64_t n_vert, const int32_t *simp
 }
 
 // Set-up of simplex s in the FP64 path: the same unwrap in box units and the
-// same cell coordinates as a plain double-precision evaluation.
-template <int D>
-SP_HD inline int setup_f64(const double *xyz, int64_t n_vert, const int32_t *simp, int64_t s, const double *rho,
+// same cell coordinates as a plain double-precision evaluation.  The inputs
+// may be float (simplices of an FP32C problem clipped in double), upcast
+// exactly.
+template <int D, typename TI = double>
+SP_HD inline int setup_f64(const TI *xyz, int64_t n_vert, const int32_t *simp, int64_t s, const TI *rho,
                            bool per_corner, const GridDev &g, bool validate, Local<double> &L)
 {
     constexpr int K = D + 1;
@@ -245,11 +247,11 @@ SP_HD inline int setup_f64(const double *xyz, int64_t n_vert, const int32_t *sim
         int64_t vi = simp[s * K + a];
         if (vi < 0 || vi >= n_vert) return SETUP_BAD_INDEX;
         for (int d = 0; d < D; ++d) {
-            x[a][d] = xyz[vi * D + d];
+            x[a][d] = (double)xyz[vi * D + d];
             double u = (x[a][d] - g.origin[d]) * g.scale[d];
             if (!finite_d(x[a][d]) || !(fabs(u) < 1.0e9)) return SETUP_NONFINITE;
         }
-        r[a] = per_corner ? rho[s * K + a] : rho[vi];
+        r[a] = (double)(per_corner ? rho[s * K + a] : rho[vi]);
         if (!finite_d(r[a])) return SETUP_NONFINITE;
     }
     for (int d = 0; d < D; ++d) {
@@ -370,9 +372,16 @@ SP_HD inline Local<T> permuted(const Local<T> &L, const SweepOrder &o)
 // current one is done, so the lanes of a wave stay busy whatever their
 // slab, column and cell counts.  On a capacity failure, fail = (i0, i1, i2)
 // is the first piece not yet deposited, in sweep order.
+//
+// Each column is built in a frame local to it: the tetrahedron is moved by
+// (-i0, -i1) before it is cut, and the column by -(its lowest cell) along z
+// once its z range is known.  The cut points then carry the rounding of
+// coordinates of a few cells instead of the simplex's span, which for
+// simplices tens of cells across is the difference between meeting the
+// FP32 bound per cell and missing it.
 struct Sweep3 {
     int sb, send, ry;
-    int ix, iy, ylo, yhi, iz, zhi, cx, cy;
+    int ix, iy, ylo, yhi, iz, zhi, cx, cy, zo;
     int fail[3];
 
     SP_HD void start(int sb_, int sc_, int ry_)
@@ -388,6 +397,7 @@ struct Sweep3 {
         zhi = -1;
         cx = sb;
         cy = 0;
+        zo = 0;
         fail[0] = ix;
         fail[1] = ry;
         fail[2] = 0;
@@ -399,11 +409,12 @@ struct Sweep3 {
     SP_HD int step(Poly3<T, MAXV, STRIDE> &P, const Local<T> &L, Dep &dep)
     {
         const int sx = L.span[0], sy = L.span[1], sz = L.span[2];
-        // build the next non-empty column
+        // build the next non-empty column (in its own frame)
         while (iz > zhi && ix < send) {
-            P.init_tet(L.v);
-            if (ix > 0 && !P.clip(0, (T)ix, true)) return -1;
-            if (ix < sx - 1 && !P.clip(0, (T)(ix + 1), false)) return -1;
+            const int fy = iy < 0 ? 0 : iy;
+            P.init_tet_at(L.v, (T)ix, (T)fy);
+            if (ix > 0 && !P.clip(0, T(0), true)) return -1;
+            if (ix < sx - 1 && !P.clip(0, T(1), false)) return -1;
             if (!P.empty() && iy < 0) {
                 T mn, mx;
                 P.range(1, mn, mx);
@@ -413,6 +424,7 @@ struct Sweep3 {
                 yhi = yhi > sy - 1 ? sy - 1 : yhi;
                 iy = ylo;
                 if (ix == sb && ry > iy) iy = ry;
+                if (iy <= yhi && iy != 0) continue;  // rebuild in the column's frame
             }
             if (P.empty() || iy > yhi) {
                 ++ix;
@@ -425,8 +437,8 @@ struct Sweep3 {
             fail[0] = ix;
             fail[1] = iy;
             fail[2] = 0;
-            if (iy > ylo && !P.clip(1, (T)iy, true)) return -1;
-            if (iy < yhi && !P.clip(1, (T)(iy + 1), false)) return -1;
+            if (iy > ylo && !P.clip(1, T(0), true)) return -1;
+            if (iy < yhi && !P.clip(1, T(1), false)) return -1;
             if (!P.empty()) {
                 T mn, mx;
                 P.range(2, mn, mx);
@@ -436,6 +448,8 @@ struct Sweep3 {
                 zhi = zhi > sz - 1 ? sz - 1 : zhi;
                 cx = ix;
                 cy = iy;
+                zo = iz;
+                if (zo != 0) P.shift(2, (T)zo);
             }
             // next column (or slab) for the following build
             if (iy >= yhi) {
@@ -452,11 +466,11 @@ struct Sweep3 {
         fail[0] = cx;
         fail[1] = cy;
         fail[2] = iz;
-        if (!P.integrate_below(2, (T)(iz + 1), last, s6, s24)) return -1;
+        if (!P.integrate_below(2, (T)(iz + 1 - zo), last, s6, s24)) return -1;
         if (s24 != T(0)) dep(cx, cy, iz, s24 / T(24));
         if (!last) {
             fail[2] = iz + 1;
-            if (!P.clip(2, (T)(iz + 1), true)) return -1;
+            if (!P.clip(2, (T)(iz + 1 - zo), true)) return -1;
             ++iz;
             if (P.empty()) zhi = iz - 1;
         } else {

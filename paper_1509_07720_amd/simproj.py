@@ -72,7 +72,7 @@ _lib.sp_create.argtypes = [ctypes.c_int, ctypes.POINTER(_V)]
 _lib.sp_create.restype = ctypes.c_int
 _lib.sp_destroy.argtypes = [_V]
 _lib.sp_destroy.restype = None
-for _name in ("sp_project_tets", "sp_project_tris"):
+for _name in ("sp_project_tets", "sp_project_tris", "sp_project_tets_noalloc"):
     getattr(_lib, _name).argtypes = [_V, ctypes.POINTER(sp_problem), ctypes.c_int, _V]
     getattr(_lib, _name).restype = ctypes.c_int
 _lib.sp_project_tets_accurate.argtypes = [_V, ctypes.POINTER(sp_problem), ctypes.c_int, ctypes.c_int,
@@ -133,6 +133,10 @@ def sp_destroy(ctx) -> None:
 
 def sp_project_tets(ctx, prob: sp_problem, prec: int, stream=None) -> int:
     return _lib.sp_project_tets(ctx, ctypes.byref(prob), int(prec), stream)
+
+
+def sp_project_tets_noalloc(ctx, prob: sp_problem, prec: int, stream=None) -> int:
+    return _lib.sp_project_tets_noalloc(ctx, ctypes.byref(prob), int(prec), stream)
 
 
 def sp_project_tris(ctx, prob: sp_problem, prec: int, stream=None) -> int:
@@ -376,8 +380,9 @@ class Context:
                     extent=(1.0, 1.0, 1.0), periodic=(True, True, True), precision: str = "fp32c",
                     rho_per_corner: bool = False, out=None, out_mass: bool = False, validate: bool = False,
                     want_total: bool = True, stream=None):
-        """Two-stage projection (sp_project_tets_amr); returns (grid,
-        total_mass, simplices per level)."""
+        """Adaptive-grid projection gathered onto the uniform grid
+        (sp_project_tets_amr); returns (grid, total_mass, simplices projected
+        at each level)."""
         import torch
 
         prec = SP_PREC_FP32C if precision == "fp32c" else SP_PREC_FP64
