@@ -38,6 +38,7 @@
 #include "simproj.h"
 #include "sp_corner.h"
 #include "sp_setup.h"
+#include "sp_wave.h"
 
 using namespace sp;
 
@@ -762,6 +763,119 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(clip_waves_p
     }
 }
 
+// The FP32 3D clip kernel with one polytope per group of 16 lanes
+// (sp_wave.h): persistent one-wave blocks of four groups; the wave claims
+// chunks of items from the class-ordered list, and every group takes the
+// next item of the chunk as soon as its sweep ends, so a group never waits
+// for the others' items.  Per loop iteration every busy group performs one
+// step of its sweep (one split, at most one piece).  An item that outgrows
+// the 16 slots is handed, from its first undeposited piece, to the overflow
+// pass of the one-polytope-per-lane kernel.
+struct GroupDep {
+    DepF32 d;
+    __device__ void operator()(int ix, int iy, int iz, float v)
+    {
+        if ((threadIdx.x & (wv::G - 1)) == 0) d(ix, iy, iz, v);
+    }
+};
+
+template <bool SINGLE>
+__global__ __launch_bounds__(WG) void k_clipw(ProbDev<float> p0, Batch b)
+{
+    static_assert(WG == 4 * wv::G, "four groups per wave");
+    const ProbDev<float> &p = p0;  // fields shared by every problem of the launch
+    __shared__ wv::GroupLDS s_g[4];
+    const int grp = (int)(threadIdx.x >> 4);
+    wv::GroupLDS *sh = &s_g[grp];
+    const unsigned total = p.cs->total;
+    unsigned *head = &p.cs->head;
+    constexpr unsigned chunk = 16u;
+    unsigned q_base = 0u, q_n = 0u, q_h = 0u;  // wave-uniform chunk state
+    bool q_done = false;
+    bool busy = false;                         // group-uniform
+    wv::Sweep S;
+    S.phase = wv::PH_IDLE;
+    GroupDep dep;
+    int64_t sid = 0;
+    int send = 0, pid = 0;
+    for (;;) {
+        const uint64_t bb = __ballot(busy);
+        // one bit per group (its lanes agree)
+        const unsigned idle = (~(unsigned)((bb & 1ull) | ((bb >> 15) & 2ull) | ((bb >> 30) & 4ull) | ((bb >> 45) & 8ull))) & 15u;
+        if (idle != 0u && q_h >= q_n && !q_done) {
+            unsigned base = 0u;
+            if (threadIdx.x == 0) base = atomicAdd(head, chunk);
+            base = __builtin_amdgcn_readfirstlane(base);
+            if (base >= total) {
+                q_done = true;
+            } else {
+                q_base = base;
+                q_n = min(chunk, total - base);
+                q_h = 0u;
+            }
+        }
+        if (!busy && q_h < q_n) {
+            // idle groups take consecutive entries in group order
+            const unsigned k = q_h + (unsigned)__builtin_popcount(idle & ((1u << grp) - 1u));
+            if (k < q_n) {
+                const unsigned it = q_base + k;
+                const uint64_t item = p.items[it];
+                sid = (int64_t)item_simplex(item);
+                const int sb = item_first(item);
+                const int sc = item_count(item);
+                send = sb + sc;
+                pid = !SINGLE && b.nprob ? (int)p.item_prob[it] : 0;
+                const ProbDev<float> q = !SINGLE && b.nprob ? static_cast<const ProbDev<float> *>(b.probs)[pid] : p0;
+                Local<float> L0;
+                double ex0[4][3];
+                if (setup_f32<3>(q.xyz, q.n_vert, q.simp, sid, q.rho, q.per_corner != 0, q.g, false, L0, ex0) ==
+                    SETUP_OK) {
+                    const SweepOrder ord = sweep_order(L0);
+                    const Local<float> L = permuted(L0, ord);
+                    double ex[4][3];
+                    permuted_exact(ex0, ord, ex);
+                    dep.d = make_dep<float>(q, L, ord);
+                    wv::sweep_start(sh, S, L, ex, sb, sc);
+                    busy = true;
+                }
+            }
+        }
+        if (q_h < q_n) q_h = min(q_n, q_h + (unsigned)__builtin_popcount(idle));
+        if (__ballot(busy) == 0ull) {
+            if (q_done) break;
+            continue;
+        }
+        if (!busy) continue;
+        if (!wv::sweep_step(sh, S, dep)) {
+            // out of slots: the rest goes to the overflow pass
+            if ((threadIdx.x & (wv::G - 1)) == 0) {
+                const unsigned k = atomicAdd(&p.cs->ovf_count, 1u);
+                if (k < OVF_CAP) {
+                    Ovf o;
+                    o.s = (int)sid;
+                    o.ix = S.fail[0];
+                    o.iy = S.fail[1];
+                    o.iz = S.fail[2];
+                    o.end = send;
+                    o.pid = pid;
+                    p.ovf[k] = o;
+                    atomicAdd(&p.es->n_overflow, 1);
+                } else {
+                    record_error(p.es, SP_E_INTERNAL);
+                    atomicAdd(&p.es->n_internal, 1);
+                }
+            }
+            S.phase = wv::PH_IDLE;
+        }
+        if (S.phase == wv::PH_IDLE) {
+            busy = false;
+            if (p.count_pieces && dep.d.count && (threadIdx.x & (wv::G - 1)) == 0)
+                atomicAdd(&p.cs->pieces, (unsigned long long)dep.d.count);  // counting runs only
+            dep.d.count = 0;
+        }
+    }
+}
+
 // Projection by first-order corner sums (Section 3.1, Appendix D), FP64:
 // one thread per simplex enumerates the vertices of all its cell pieces
 // (simplex corners, edge-face and facet-edge crossings, grid points inside)
@@ -1331,6 +1445,7 @@ struct sp_ctx {
     double *dummy_total;
     Tuning tune;
     int profiling;
+    int per_lane_clip;  // 1: the one-polytope-per-lane FP32 clip kernel instead of the group one
     int prof_calls;
     int last_clip_blocks;
     // (start, end) events per recorded stage and per whole call
@@ -1441,6 +1556,8 @@ extern "C" sp_status sp_create(int hip_device, sp_ctx **ctx)
     if (const char *e = getenv("SIMPROJ_CLIP_BLOCKS_PER_CU")) c->tune.chunks_per_cu = atoi(e) > 0 ? atoi(e) : 0;
     if (const char *e = getenv("SIMPROJ_ITEM_PIECES")) c->tune.item_pieces = atoi(e) > 0 ? atoi(e) : 0;
     c->profiling = 0;
+    c->per_lane_clip = 0;
+    if (const char *e = getenv("SIMPROJ_PER_LANE_CLIP")) c->per_lane_clip = atoi(e) != 0;
     c->prof_calls = 0;
     c->last_clip_blocks = 0;
     c->noalloc = nullptr;
@@ -1726,15 +1843,27 @@ static void enqueue(sp_ctx *ctx, const Prepared<T> *v, int nv, const Batch &b, i
         const bool one = fp32 && single;
         auto kclip = one ? k_clip<D, T, MAXV3, true> : k_clip<D, T, MAXV3, false>;
         auto kretry = D == 3 ? (one ? k_clip<D, T, MAXV3_BIG, true> : k_clip<D, T, MAXV3_BIG, false>) : kclip;
+        // 3D FP32: the group kernel
+        const bool grouped = D == 3 && fp32 && !ctx->per_lane_clip;
         int occ = 0;
-        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kclip, WG, 0);
+        if constexpr (D == 3 && sizeof(T) == 4) {
+            if (grouped)
+                (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, one ? k_clipw<true> : k_clipw<false>, WG, 0);
+        }
+        if (!grouped) (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kclip, WG, 0);
         if (occ < 1) occ = 1;
         const int cpc = ctx->tune.chunks_per_cu > 0 ? ctx->tune.chunks_per_cu : occ;
         const int blocks = ctx->num_cu * cpc;
         ctx->last_clip_blocks = blocks;
         {
             StageTimer t = timer(ST_CLIP);
-            hipLaunchKernelGGL(kclip, dim3(blocks), dim3(WG), 0, stream, p0, b, 0);
+            if constexpr (D == 3 && sizeof(T) == 4) {
+                if (grouped) {
+                    if (one) hipLaunchKernelGGL(k_clipw<true>, dim3(blocks), dim3(WG), 0, stream, p0, b);
+                    else hipLaunchKernelGGL(k_clipw<false>, dim3(blocks), dim3(WG), 0, stream, p0, b);
+                }
+            }
+            if (!grouped) hipLaunchKernelGGL(kclip, dim3(blocks), dim3(WG), 0, stream, p0, b, 0);
         }
         {
             StageTimer t = timer(ST_RETRY);

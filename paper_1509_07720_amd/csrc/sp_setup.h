@@ -168,9 +168,13 @@ SP_HD inline float orient2_f(const V4<float> *v)
 // Set-up of simplex s in the FP32 path.  D = 2 or 3.  Every check runs
 // whatever `validate` says (a bad index or a non-finite coordinate must never
 // reach the sweep); the caller decides whether to report the status.
+//
+// ex (optional, D = 3): the corners' local coordinates without rounding,
+// (k - anchor) + fraction in FP64, in the same corner order as L.
 template <int D>
 SP_HD inline int setup_f32(const float *xyz, int64_t n_vert, const int32_t *simp, int64_t s, const float *rho,
-                           bool per_corner, const GridDev &g, bool validate, Local<float> &L)
+                           bool per_corner, const GridDev &g, bool validate, Local<float> &L,
+                           double (*ex)[3] = nullptr)
 {
     constexpr int K = D + 1;
     int k[4][3];
@@ -207,6 +211,7 @@ SP_HD inline int setup_f32(const float *xyz, int64_t n_vert, const int32_t *simp
             else if (d == 1) L.v[a].y = l;
             else L.v[a].z = l;
             lmax = l > lmax ? l : lmax;
+            if (ex) ex[a][d] = (double)(k[a][d] - kmin) + (double)f[a][d];
         }
         if (!(lmax < (float)MAX_SPAN) || (g.periodic[d] && !(lmax < 0.5f * (float)g.dims[d]))) return SETUP_BAD_SPAN;
         L.anchor[d] = kmin;
@@ -227,6 +232,12 @@ SP_HD inline int setup_f32(const float *xyz, int64_t n_vert, const int32_t *simp
         L.v[1] = L.v[2];
         L.v[2] = t;
         det = -det;
+        if (ex)
+            for (int d = 0; d < 3; ++d) {
+                const double u = ex[1][d];
+                ex[1][d] = ex[2][d];
+                ex[2][d] = u;
+            }
     }
     L.det = det;
     return SETUP_OK;
@@ -358,6 +369,20 @@ SP_HD inline Local<T> permuted(const Local<T> &L, const SweepOrder &o)
         M.v[2] = t;
     }
     return M;
+}
+
+// Exact corners relabelled as permuted() relabels the set-up.
+SP_HD inline void permuted_exact(const double (*ex)[3], const SweepOrder &o, double (*out)[3])
+{
+    for (int k = 0; k < 4; ++k)
+        for (int d = 0; d < 3; ++d) out[k][d] = sel3(ex[k][0], ex[k][1], ex[k][2], o.ax[d]);
+    const bool odd = !((o.ax[0] == 0 && o.ax[1] == 1) || (o.ax[0] == 1 && o.ax[1] == 2) || (o.ax[0] == 2 && o.ax[1] == 0));
+    if (odd)
+        for (int d = 0; d < 3; ++d) {
+            const double u = out[1][d];
+            out[1][d] = out[2][d];
+            out[2][d] = u;
+        }
 }
 
 // Sweep of one 3D simplex over the slabs [sb, sb+sc) of its outermost axis,

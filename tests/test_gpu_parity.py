@@ -113,7 +113,7 @@ def test_full_size_soup_every_cell(ctx):
         del got
 
 
-def _needles(n, grid, seed, lmin=64.0, lmax=130.0):
+def _needles(n, grid, seed, lmin=67.0, lmax=130.0):
     """n tetrahedra 64-130 cells long along a random grid axis and 1-3 cells
     across (small bounding boxes, so the brute-force oracle stays quick),
     random positions in a periodic unit box, random positive corner
