@@ -598,18 +598,19 @@ SP_HD inline void sweep_start(GroupLDS *sh, Sweep &S, const Local<float> &L, con
     // the tetrahedron in the frame of slab sb: neighbours counter-clockwise
     // from outside, face j of vertex v opposite the corner not in
     // {v, neighbour j-1, neighbour j}
-    const int nbs[4][3] = {{1, 3, 2}, {2, 3, 0}, {0, 3, 1}, {1, 2, 0}};
+    // (neighbours of corner v: {1,3,2}, {2,3,0}, {0,3,1}, {1,2,0}, as nibble
+    // tables indexed by the lane, and the corner as selects, so that nothing
+    // is indexed by the lane at run time)
     WV_LANES
     {
         const int v = wv_lane();
         if (v < 4) {
+            const int a = (0x1021 >> (4 * v)) & 15, b = (0x2333 >> (4 * v)) & 15, c = (0x0102 >> (4 * v)) & 15;
             SlotD t;
-            t.x = X[v][0] - (double)sb;
-            t.y = X[v][1];
-            t.z = X[v][2];
-            int lab[3];
-            for (int j = 0; j < 3; ++j) lab[j] = 6 - v - nbs[v][(j + 2) % 3] - nbs[v][j];
-            t.w = wpack(nbs[v][0], nbs[v][1], nbs[v][2], lab[0], lab[1], lab[2]);
+            t.x = (v == 0 ? X[0][0] : v == 1 ? X[1][0] : v == 2 ? X[2][0] : X[3][0]) - (double)sb;
+            t.y = v == 0 ? X[0][1] : v == 1 ? X[1][1] : v == 2 ? X[2][1] : X[3][1];
+            t.z = v == 0 ? X[0][2] : v == 1 ? X[1][2] : v == 2 ? X[2][2] : X[3][2];
+            t.w = wpack(a, b, c, 6 - v - c - a, 6 - v - a - b, 6 - v - b - c);
             sh->bd[S.r0][v] = t;
         }
     }
