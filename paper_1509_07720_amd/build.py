@@ -41,7 +41,7 @@ def build_library(out: str = OUT, extra=()) -> str:
     return out
 
 
-KERNEL_SOURCES = ("simproj.hip", "sp_poly.h", "sp_setup.h")
+KERNEL_SOURCES = ("simproj.hip", "sp_poly.h", "sp_setup.h", "sp_wave.h", "sp_corner.h")
 
 
 def kernel_source_hash() -> str:

@@ -508,7 +508,12 @@ __global__ __launch_bounds__(256) void k_setup(ProbDev<T> p0, Batch b)
                 est_all = piece_estimate<T, D>(L);
                 if (sx > 0) {
                     const float per_slab = est_all / (float)sx;
-                    const int G = (int)fminf((float)p.slab_group, fmaxf(1.0f, floorf(p.item_pieces / per_slab)));
+                    // the few simplices routed to FP64 go one slab per item:
+                    // whole, each would hold one lane for its hundreds of
+                    // pieces while the rest of the launch waits for it
+                    const int G = wide ? 1
+                                       : (int)fminf((float)p.slab_group,
+                                                    fmaxf(1.0f, floorf(p.item_pieces / per_slab)));
                     nit = (sx + G - 1) / G;
                     if (nit > MAX_ITEMS) nit = MAX_ITEMS;  // 12-bit field of the item count
                 }
@@ -1445,7 +1450,7 @@ struct sp_ctx {
     double *dummy_total;
     Tuning tune;
     int profiling;
-    int per_lane_clip;  // 1: the one-polytope-per-lane FP32 clip kernel instead of the group one
+    int group_clip;  // 1: the FP32 3D clip runs one polytope per 16 lanes (k_clipw) instead of one per lane
     int prof_calls;
     int last_clip_blocks;
     // (start, end) events per recorded stage and per whole call
@@ -1556,8 +1561,8 @@ extern "C" sp_status sp_create(int hip_device, sp_ctx **ctx)
     if (const char *e = getenv("SIMPROJ_CLIP_BLOCKS_PER_CU")) c->tune.chunks_per_cu = atoi(e) > 0 ? atoi(e) : 0;
     if (const char *e = getenv("SIMPROJ_ITEM_PIECES")) c->tune.item_pieces = atoi(e) > 0 ? atoi(e) : 0;
     c->profiling = 0;
-    c->per_lane_clip = 0;
-    if (const char *e = getenv("SIMPROJ_PER_LANE_CLIP")) c->per_lane_clip = atoi(e) != 0;
+    c->group_clip = 0;
+    if (const char *e = getenv("SIMPROJ_GROUP_CLIP")) c->group_clip = atoi(e) != 0;
     c->prof_calls = 0;
     c->last_clip_blocks = 0;
     c->noalloc = nullptr;
@@ -1843,8 +1848,9 @@ static void enqueue(sp_ctx *ctx, const Prepared<T> *v, int nv, const Batch &b, i
         const bool one = fp32 && single;
         auto kclip = one ? k_clip<D, T, MAXV3, true> : k_clip<D, T, MAXV3, false>;
         auto kretry = D == 3 ? (one ? k_clip<D, T, MAXV3_BIG, true> : k_clip<D, T, MAXV3_BIG, false>) : kclip;
-        // 3D FP32: the group kernel
-        const bool grouped = D == 3 && fp32 && !ctx->per_lane_clip;
+        // 3D FP32: the group kernel when asked for (it measured slower than
+        // one polytope per lane on every workload tried)
+        const bool grouped = D == 3 && fp32 && ctx->group_clip;
         int occ = 0;
         if constexpr (D == 3 && sizeof(T) == 4) {
             if (grouped)

@@ -385,6 +385,43 @@ SP_HD inline void permuted_exact(const double (*ex)[3], const SweepOrder &o, dou
         }
 }
 
+// y range of a simplex's part in slab ix of its sweep (x in [ix, ix + 1),
+// unbounded below for the first slab and above for the last), in its anchor
+// frame: over its corners inside the slab and the points where its edges
+// cross the slab's planes.  mn > mx: the slab is empty.  Rounding can put a
+// bound a hair off; the sweep leaves its first column open below and its
+// last open above, so a sliver beyond a bound still lands in a column.
+template <typename T>
+SP_HD inline void slab_y_range(const V4<T> *v, int ix, int sx, T &mn, T &mx)
+{
+    const bool lo = ix > 0, hi = ix < sx - 1;
+    const T xl = (T)ix, xu = (T)(ix + 1);
+    mn = T(INFINITY);
+    mx = T(-INFINITY);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const bool in = (!lo || v[k].x >= xl) && (!hi || v[k].x <= xu);
+        mn = in ? sp_fmin(mn, v[k].y) : mn;
+        mx = in ? sp_fmax(mx, v[k].y) : mx;
+    }
+#pragma unroll
+    for (int e = 0; e < 6; ++e) {
+        const int a = e < 3 ? 0 : (e < 5 ? 1 : 2);
+        const int b = e < 3 ? e + 1 : (e < 5 ? e - 1 : 3);
+        const T xa = v[a].x, xb = v[b].x, ya = v[a].y, yb = v[b].y;
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            const T c = side ? xu : xl;
+            const bool on = side ? hi : lo;
+            if (on && ((xa < c) != (xb < c))) {
+                const T y = ya + (c - xa) / (xb - xa) * (yb - ya);
+                mn = sp_fmin(mn, y);
+                mx = sp_fmax(mx, y);
+            }
+        }
+    }
+}
+
 // Sweep of one 3D simplex over the slabs [sb, sb+sc) of its outermost axis,
 // starting at column ry of the first slab.  The deposit receives each
 // piece's integral of rho in cell-volume units at its local cell indices
@@ -398,9 +435,11 @@ SP_HD inline void permuted_exact(const double (*ex)[3], const SweepOrder &o, dou
 // slab, column and cell counts.  On a capacity failure, fail = (i0, i1, i2)
 // is the first piece not yet deposited, in sweep order.
 //
-// Each column is built in a frame local to it: the tetrahedron is moved by
-// (-i0, -i1) before it is cut, and the column by -(its lowest cell) along z
-// once its z range is known.  The cut points then carry the rounding of
+// Each column is cut out of the simplex afresh, in a frame local to it: the
+// tetrahedron is moved by (-i0, -i1) and clipped by the slab's and the
+// column's planes (the slab's y range comes from the corners, not from a
+// clipped slab), and the column is moved by -(its lowest cell) along z once
+// its z range is known.  The cut points then carry the rounding of
 // coordinates of a few cells instead of the simplex's span, which for
 // simplices tens of cells across is the difference between meeting the
 // FP32 bound per cell and missing it.
@@ -436,32 +475,33 @@ struct Sweep3 {
         const int sx = L.span[0], sy = L.span[1], sz = L.span[2];
         // build the next non-empty column (in its own frame)
         while (iz > zhi && ix < send) {
-            const int fy = iy < 0 ? 0 : iy;
-            P.init_tet_at(L.v, (T)ix, (T)fy);
-            if (ix > 0 && !P.clip(0, T(0), true)) return -1;
-            if (ix < sx - 1 && !P.clip(0, T(1), false)) return -1;
-            if (!P.empty() && iy < 0) {
+            if (iy < 0) {
+                // a new slab: its columns
                 T mn, mx;
-                P.range(1, mn, mx);
-                ylo = (int)floor(mn);
-                yhi = (int)floor(mx);
-                ylo = ylo < 0 ? 0 : ylo;
-                yhi = yhi > sy - 1 ? sy - 1 : yhi;
-                iy = ylo;
-                if (ix == sb && ry > iy) iy = ry;
-                if (iy <= yhi && iy != 0) continue;  // rebuild in the column's frame
-            }
-            if (P.empty() || iy > yhi) {
-                ++ix;
-                iy = -1;
-                fail[0] = ix;
-                fail[1] = 0;
-                fail[2] = 0;
-                continue;
+                slab_y_range(L.v, ix, sx, mn, mx);
+                if (mn <= mx) {
+                    ylo = (int)floor(mn);
+                    yhi = (int)floor(mx);
+                    ylo = ylo < 0 ? 0 : (ylo > sy - 1 ? sy - 1 : ylo);
+                    yhi = yhi > sy - 1 ? sy - 1 : (yhi < ylo ? ylo : yhi);
+                    iy = ylo;
+                    if (ix == sb && ry > iy) iy = ry;
+                }
+                if (mn > mx || iy > yhi) {
+                    ++ix;
+                    iy = -1;
+                    fail[0] = ix;
+                    fail[1] = 0;
+                    fail[2] = 0;
+                    continue;
+                }
             }
             fail[0] = ix;
             fail[1] = iy;
             fail[2] = 0;
+            P.init_tet_at(L.v, (T)ix, (T)iy);
+            if (ix > 0 && !P.clip(0, T(0), true)) return -1;
+            if (ix < sx - 1 && !P.clip(0, T(1), false)) return -1;
             if (iy > ylo && !P.clip(1, T(0), true)) return -1;
             if (iy < yhi && !P.clip(1, T(1), false)) return -1;
             if (!P.empty()) {
