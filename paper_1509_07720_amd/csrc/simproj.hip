@@ -495,7 +495,7 @@ __global__ __launch_bounds__(256) void k_setup(ProbDev<T> p0, Batch b)
                         // of the FP64 set-up, which the clip will repeat
                         Local<double> Lw;
                         if (setup_any<D>(p, s, false, Lw) == SETUP_OK) {
-                            const int aw = sweep_order(Lw).ax[0];
+                            const int aw = sweep_order(Lw, true).ax[0];
                             sx = D == 3 ? sel3(Lw.span[0], Lw.span[1], Lw.span[2], aw) : Lw.span[0];
                         } else {
                             sx = 0;  // the FP64 set-up drops it (zero volume, span): no items
@@ -638,8 +638,9 @@ constexpr int clip_waves_per_simd() { return D == 3 && sizeof(T) == 4 && MAXV <=
 
 // T is the arithmetic of the clip, TI that of the problem (inputs and
 // grids).  TI = float with T = double is the FP64 route of an FP32C problem:
-// it takes the CLS_WIDE items at the head of the list, and a polytope that
-// outgrows its slots there is an internal error (it runs with 32 slots).
+// it takes the CLS_WIDE items at the head of the list (one slab each, swept
+// with the simplex's longest axis outermost), and a polytope that outgrows
+// its slots there is an internal error (it runs with 32 slots).
 template <int D, typename T, int MAXV, bool SINGLE, typename TI = T>
 __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(clip_waves_per_simd<D, T, MAXV>()))) void k_clip(
     ProbDev<TI> p0, Batch b, int overflow_pass)
@@ -710,7 +711,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(clip_waves_p
                 const ProbDev<TI> q = !SINGLE && b.nprob ? static_cast<const ProbDev<TI> *>(b.probs)[pid] : p0;
                 Local<T> L0;
                 if (setup_any<D>(q, sid, false, L0) == SETUP_OK) {
-                    const SweepOrder ord = D == 3 ? sweep_order(L0) : kIdentity;
+                    const SweepOrder ord = D == 3 ? sweep_order(L0, WIDE && !overflow_pass) : kIdentity;
                     L = D == 3 ? permuted(L0, ord) : L0;
                     if (D == 3) P3.set_density(L.v);
                     dep = make_dep<T>(q, L, ord);

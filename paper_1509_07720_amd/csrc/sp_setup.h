@@ -316,13 +316,16 @@ SP_HD inline int setup_f64(const TI *xyz, int64_t n_vert, const int32_t *simp, i
 
 // Order in which a simplex is swept: outermost axis first, innermost last.
 // The innermost axis is the one of largest extent, which makes the columns
-// (and so the polytope rebuilds) fewest.
+// (and so the polytope rebuilds) fewest.  With outer_longest the largest
+// extent goes outermost instead: more columns, but as many slabs as the
+// simplex is long, so that a long simplex cut into one-slab work items
+// spreads over many lanes.
 struct SweepOrder {
     int ax[3];
 };
 
 template <typename T>
-SP_HD inline SweepOrder sweep_order(const Local<T> &L)
+SP_HD inline SweepOrder sweep_order(const Local<T> &L, bool outer_longest = false)
 {
     // sort axes by span, ascending; ties keep x, y, z order (written with
     // compares on values only, so nothing is indexed at run time)
@@ -334,6 +337,11 @@ SP_HD inline SweepOrder sweep_order(const Local<T> &L)
     o.ax[0] = r0 == 0 ? 0 : (r1 == 0 ? 1 : 2);
     o.ax[1] = r0 == 1 ? 0 : (r1 == 1 ? 1 : 2);
     o.ax[2] = r0 == 2 ? 0 : (r1 == 2 ? 1 : 2);
+    if (outer_longest) {
+        const int t = o.ax[0];
+        o.ax[0] = o.ax[2];
+        o.ax[2] = t;
+    }
     return o;
 }
 
