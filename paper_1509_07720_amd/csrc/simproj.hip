@@ -55,13 +55,15 @@ constexpr int NCLS = 16;     // cost classes
 // other simplex uses; their work items come first in the list.
 constexpr int WIDE_SPAN = 64;
 constexpr int CLS_WIDE = NCLS - 1;
-// Polytope vertex slots per lane.  FP32: 17 slots (17 KB of LDS per wave)
-// let 9 waves share a CU when the kernel keeps to 168 VGPRs (3 waves per
-// SIMD); the rare polytope that needs more is finished by the 32-slot
-// kernel.  FP64 (32-byte slots) is bound to 4-5 waves by its LDS either
-// way and keeps 18 slots, which it never overflowed in the tests.
+// Polytope vertex slots per lane.  A cut frees the removed vertices it no
+// longer reads before it places new ones, so its peak stays near the larger
+// of the two polytopes.  FP32: 14 slots (14 KB of LDS per wave) let 11 waves
+// share a CU when the kernel keeps to 168 VGPRs (3 waves per SIMD); the
+// kernel is latency bound, and every wave counts (9 waves ran 9 % faster
+// than 8).  No 10M-tet soup item needed more than 14; one that does is
+// finished by the 32-slot kernel.  FP64 (32-byte slots): 15 slots, 5 waves.
 template <typename T>
-constexpr int maxv3() { return sizeof(T) == 4 ? 17 : 18; }
+constexpr int maxv3() { return sizeof(T) == 4 ? 14 : 15; }
 constexpr int MAXV3_BIG = 32;
 constexpr int MAXP2 = 12;    // polygon vertices per lane and buffer (peak 8)
 constexpr int OVF_CAP = 1 << 20;  // overflow records per launch (24 MB of scratch)

@@ -332,9 +332,22 @@ struct Poly3 {
             live = 0u;
             return true;
         }
-        const uint32_t gone = live & ~keep;
+        uint32_t gone = live & ~keep;
         uint32_t freem = ~live & SLOTS;
         uint32_t fresh = 0u;
+        // removed vertices with no kept neighbour are never read again: their
+        // slots are free before any new vertex is placed, which keeps the
+        // peak slot count at about the larger of the two polytopes' sizes
+        {
+            uint32_t inner = 0u;
+            for (uint32_t w = gone; w; w &= w - 1u) {
+                const int x = lowbit(w);
+                const uint32_t nbx = N(x);
+                if (!(((keep >> nbr(nbx, 0)) | (keep >> nbr(nbx, 1)) | (keep >> nbr(nbx, 2))) & 1u)) inner |= 1u << x;
+            }
+            freem |= inner;
+            gone &= ~inner;
+        }
         // one new vertex per edge between a removed and a kept vertex; the
         // removed side is usually the smaller one (the piece being cut off).
         // A removed vertex is dead once its own edges are done (its position
