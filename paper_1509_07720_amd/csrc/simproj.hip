@@ -262,6 +262,31 @@ struct DepFor<double> {
 // ---------------------------------------------------------------------------
 // problem description as the kernels see it
 
+// Per-simplex set-up handed from k_setup to the 3D clip kernels: the local
+// frame relabelled to the sweep order, that order and the density gradient
+// (the FP64 solve through the corner values), so that a clip lane starting
+// a simplex loads one record instead of repeating the set-up.  Written for
+// every simplex that gets work items, except those routed to FP64.
+template <typename T>
+struct SimplexRec {
+    V4<T> v[4];
+    int anchor[3];
+    int span[3];
+    T det;
+    int order;  // sweep axes: ax[0] | ax[1] << 2 | ax[2] << 4
+    double gd[3];
+};
+
+SP_HD inline int pack_order(const SweepOrder &o) { return o.ax[0] | (o.ax[1] << 2) | (o.ax[2] << 4); }
+SP_HD inline SweepOrder unpack_order(int w)
+{
+    SweepOrder o;
+    o.ax[0] = w & 3;
+    o.ax[1] = (w >> 2) & 3;
+    o.ax[2] = (w >> 4) & 3;
+    return o;
+}
+
 template <typename T>
 struct ProbDev {
     const T *xyz;
@@ -275,6 +300,7 @@ struct ProbDev {
     T *out;        // hi (FP32C) or the grid (FP64)
     float *lo;     // FP32C low grid
     uint32_t *tinfo;        // this problem's slice
+    SimplexRec<T> *rec;     // this problem's slice (3D)
     uint64_t *items;        // shared by all problems of a launch
     uint16_t *item_prob;    // problem of each item (batches only)
     unsigned extra_cap;
@@ -488,9 +514,24 @@ __global__ __launch_bounds__(256) void k_setup(ProbDev<T> p0, Batch b)
                 }
                 if (p.count_pieces) atomicAdd(&p.cs->pieces, 1ull);
             } else {
-                const int a0 = sweep_order(L).ax[0];
+                const SweepOrder ord = sweep_order(L);
                 wide = sizeof(T) == 4 && max(L.span[0], max(L.span[1], L.span[2])) >= WIDE_SPAN;
-                sx = D == 3 ? sel3(L.span[0], L.span[1], L.span[2], a0) : L.span[0];
+                sx = D == 3 ? sel3(L.span[0], L.span[1], L.span[2], ord.ax[0]) : L.span[0];
+                if constexpr (D == 3) {
+                    if (!wide) {
+                        const Local<T> M = permuted(L, ord);
+                        SimplexRec<T> r;
+                        for (int k = 0; k < 4; ++k) r.v[k] = M.v[k];
+                        for (int d = 0; d < 3; ++d) {
+                            r.anchor[d] = M.anchor[d];
+                            r.span[d] = M.span[d];
+                        }
+                        r.det = M.det;
+                        r.order = pack_order(ord);
+                        density_gradient(M.v, r.gd);
+                        p.rec[s] = r;
+                    }
+                }
                 if constexpr (sizeof(T) == 4) {
                     if (wide) {
                         // the items of a simplex routed to FP64 count the slabs
@@ -633,7 +674,7 @@ __global__ __launch_bounds__(256) void k_scatter(ProbDev<T> p0, Batch b)
 // performs one sweep step (a column build if due, then one piece).
 //
 // Waves per SIMD the compiler must leave room for: 3 (at most 168 VGPRs) for
-// the 17-slot FP32 polytopes, whose LDS admits 9 waves per CU; the other
+// the 14-slot FP32 polytopes, whose LDS admits 11 waves per CU; the other
 // forms are bound by their LDS to 2 or fewer anyway.
 template <int D, typename T, int MAXV>
 constexpr int clip_waves_per_simd() { return D == 3 && sizeof(T) == 4 && MAXV <= 17 ? 3 : 1; }
@@ -711,11 +752,32 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(clip_waves_p
                     pid = !SINGLE && b.nprob ? (int)p.item_prob[it] : 0;
                 }
                 const ProbDev<TI> q = !SINGLE && b.nprob ? static_cast<const ProbDev<TI> *>(b.probs)[pid] : p0;
-                Local<T> L0;
-                if (setup_any<D>(q, sid, false, L0) == SETUP_OK) {
-                    const SweepOrder ord = D == 3 ? sweep_order(L0, WIDE && !overflow_pass) : kIdentity;
-                    L = D == 3 ? permuted(L0, ord) : L0;
-                    if (D == 3) P3.set_density(L.v);
+                bool ok;
+                SweepOrder ord = kIdentity;
+                if constexpr (D == 3 && !WIDE) {
+                    // the set-up k_setup left for this simplex
+                    const SimplexRec<T> r = q.rec[sid];
+                    for (int k = 0; k < 4; ++k) L.v[k] = r.v[k];
+                    for (int d = 0; d < 3; ++d) {
+                        L.anchor[d] = r.anchor[d];
+                        L.span[d] = r.span[d];
+                    }
+                    L.det = r.det;
+                    ord = unpack_order(r.order);
+                    P3.set_density(L.v, r.gd);
+                    ok = true;
+                } else {
+                    Local<T> L0;
+                    ok = setup_any<D>(q, sid, false, L0) == SETUP_OK;
+                    if (ok && D == 3) {
+                        ord = sweep_order(L0, WIDE);
+                        L = permuted(L0, ord);
+                        P3.set_density(L.v);
+                    } else if (ok) {
+                        L = L0;
+                    }
+                }
+                if (ok) {
                     dep = make_dep<T>(q, L, ord);
                     if (overflow_pass) {
                         dep.suppress_ix = sb;
@@ -1740,6 +1802,8 @@ static sp_status prepare(sp_ctx *ctx, const sp_problem *probs, int n, Prepared<T
     size_t off = 0;
     const size_t o_tinfo = off;
     if (work_lists) off = align_up(off + sizeof(uint32_t) * (size_t)(ntotal > 0 ? ntotal : 1));
+    const size_t o_rec = off;
+    if (work_lists && D == 3) off = align_up(off + sizeof(SimplexRec<T>) * (size_t)(ntotal > 0 ? ntotal : 1));
     const size_t o_items = off;
     off = align_up(off + sizeof(uint64_t) * nitems);
     const size_t o_iprob = off;
@@ -1792,6 +1856,7 @@ static sp_status prepare(sp_ctx *ctx, const sp_problem *probs, int n, Prepared<T
             }
         }
         p.tinfo = work_lists ? reinterpret_cast<uint32_t *>(base + o_tinfo) + toff : nullptr;
+        p.rec = work_lists && D == 3 ? reinterpret_cast<SimplexRec<T> *>(base + o_rec) + toff : nullptr;
         toff += prob->n_simplex;
         p.items = work_lists ? reinterpret_cast<uint64_t *>(base + o_items) : nullptr;
         p.item_prob = batched && work_lists ? reinterpret_cast<uint16_t *>(base + o_iprob) : nullptr;

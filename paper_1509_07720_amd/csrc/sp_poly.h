@@ -168,6 +168,31 @@ SP_HD inline S4<T> isect3(const S4<T> &a, const S4<T> &b, int ax, T c)
     return q;
 }
 
+// Gradient of the affine density through the four corner values of a
+// tetrahedron: g solves g . (v_k - v_0) = r_k - r_0 (Cramer's rule in FP64
+// on the exact differences of the corner data; 0 for a flat tetrahedron).
+template <typename T>
+SP_HD inline void density_gradient(const V4<T> *v, double *gd)
+{
+    double e[3][3], dr[3];
+    for (int k = 0; k < 3; ++k) {
+        e[k][0] = (double)v[k + 1].x - (double)v[0].x;
+        e[k][1] = (double)v[k + 1].y - (double)v[0].y;
+        e[k][2] = (double)v[k + 1].z - (double)v[0].z;
+        dr[k] = (double)v[k + 1].r - (double)v[0].r;
+    }
+    double c[3][3];  // c[k] = e[k+1] x e[k+2]
+    for (int k = 0; k < 3; ++k) {
+        const double *a = e[(k + 1) % 3], *b = e[(k + 2) % 3];
+        c[k][0] = a[1] * b[2] - a[2] * b[1];
+        c[k][1] = a[2] * b[0] - a[0] * b[2];
+        c[k][2] = a[0] * b[1] - a[1] * b[0];
+    }
+    const double det = e[0][0] * c[0][0] + e[0][1] * c[0][1] + e[0][2] * c[0][2];
+    const double inv = det != 0.0 ? 1.0 / det : 0.0;
+    for (int d = 0; d < 3; ++d) gd[d] = (dr[0] * c[0][d] + dr[1] * c[1][d] + dr[2] * c[2][d]) * inv;
+}
+
 // Vertex storage with a stride: on the GPU each lane's polytope is spread
 // over LDS with stride = lanes per block, so that lanes touching the same
 // slot hit consecutive words.  Slots in use are marked in `live`; a cut
@@ -203,29 +228,18 @@ struct Poly3 {
     }
     SP_HD bool empty() const { return live == 0u; }
 
-    // The affine density through the four corner values of a tetrahedron:
-    // g solves g . (v_k - v_0) = r_k - r_0 (Cramer's rule in FP64 on the
-    // exact differences of the corner data).
+    // The affine density through the four corner values of a tetrahedron.
     SP_HD void set_density(const V4<T> *v)
     {
-        double e[3][3], dr[3];
-        for (int k = 0; k < 3; ++k) {
-            e[k][0] = (double)v[k + 1].x - (double)v[0].x;
-            e[k][1] = (double)v[k + 1].y - (double)v[0].y;
-            e[k][2] = (double)v[k + 1].z - (double)v[0].z;
-            dr[k] = (double)v[k + 1].r - (double)v[0].r;
-        }
-        double c[3][3];  // c[k] = e[k+1] x e[k+2]
-        for (int k = 0; k < 3; ++k) {
-            const double *a = e[(k + 1) % 3], *b = e[(k + 2) % 3];
-            c[k][0] = a[1] * b[2] - a[2] * b[1];
-            c[k][1] = a[2] * b[0] - a[0] * b[2];
-            c[k][2] = a[0] * b[1] - a[1] * b[0];
-        }
-        const double det = e[0][0] * c[0][0] + e[0][1] * c[0][1] + e[0][2] * c[0][2];
-        const double inv = det != 0.0 ? 1.0 / det : 0.0;
+        double grad[3];
+        density_gradient(v, grad);
+        set_density(v, grad);
+    }
+    // The same with the gradient given (as density_gradient computes it).
+    SP_HD void set_density(const V4<T> *v, const double *grad)
+    {
         for (int d = 0; d < 3; ++d) {
-            gd[d] = (dr[0] * c[0][d] + dr[1] * c[1][d] + dr[2] * c[2][d]) * inv;
+            gd[d] = grad[d];
             g[d] = (T)gd[d];
         }
         r0 = (double)v[0].r;
