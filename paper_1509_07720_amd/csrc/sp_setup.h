@@ -421,11 +421,11 @@ SP_HD inline void slab_y_range(const V4<T> *v, int ix, int sx, T &mn, T &mx)
         for (int side = 0; side < 2; ++side) {
             const T c = side ? xu : xl;
             const bool on = side ? hi : lo;
-            if (on && ((xa < c) != (xb < c))) {
-                const T y = ya + (c - xa) / (xb - xa) * (yb - ya);
-                mn = sp_fmin(mn, y);
-                mx = sp_fmax(mx, y);
-            }
+            // (the hardware reciprocal: a bound only needs to be near)
+            const bool cut = on && ((xa < c) != (xb < c));
+            const T y = ya + (c - xa) * sp_rcp(cut ? xb - xa : T(1)) * (yb - ya);
+            mn = cut ? sp_fmin(mn, y) : mn;
+            mx = cut ? sp_fmax(mx, y) : mx;
         }
     }
 }
@@ -508,10 +508,16 @@ struct Sweep3 {
             fail[1] = iy;
             fail[2] = 0;
             P.init_tet_at(L.v, (T)ix, (T)iy);
-            if (ix > 0 && !P.clip(0, T(0), true)) return -1;
-            if (ix < sx - 1 && !P.clip(0, T(1), false)) return -1;
-            if (iy > ylo && !P.clip(1, T(0), true)) return -1;
-            if (iy < yhi && !P.clip(1, T(1), false)) return -1;
+            // the slab's and the column's planes, those that cut: one clip
+            // call in a loop, so that lanes needing different planes cut
+            // together
+            for (uint32_t cuts = (ix > 0 ? 1u : 0u) | (ix < sx - 1 ? 2u : 0u) | (iy > ylo ? 4u : 0u) |
+                                 (iy < yhi ? 8u : 0u);
+                 cuts; cuts &= cuts - 1u) {
+                const int k = __builtin_ctz(cuts);
+                const bool lower = (k & 1) == 0;  // a lower plane keeps what is above it
+                if (!P.clip(k >> 1, lower ? T(0) : T(1), lower)) return -1;
+            }
             if (!P.empty()) {
                 T mn, mx;
                 P.range(2, mn, mx);
