@@ -39,13 +39,16 @@ sys.path.insert(0, ROOT)
 COUNTERS = os.path.join(ROOT, "profiles", "k_clip_soup10M_256_fp32c_counters.md")
 MBENCH = os.path.join(ROOT, "paper_1509_07720_amd", "mbench")
 
-# Algorithmic work per deposited piece, FP32 operations: the cut that
-# separates the piece (about 6 new vertices x 10 flops: a division and four
-# fused multiply-adds for position and density), the classification of the
-# ~12 remaining vertices against the plane (12), and the integration of the
-# piece as a fan of ~12 tetrahedra (12 x 20 flops: a 3x3 determinant and the
-# density sum).  See the design notes for the derivation.
-FLOPS_PER_PIECE = 60 + 12 + 240
+# Algorithmic work per deposited piece: the slab recursion's counted
+# intersection points (10 flops: a division and four fused multiply-adds),
+# vertex classifications (2) and fan tetrahedra (20: a determinant and a
+# density sum), per piece, on samples of each workload's recipe (stored by
+# tests/golden/make_work_counts.py from the oracle's work-count model).
+WORK_COUNTS = os.path.join(ROOT, "tests", "golden", "work_counts.json")
+with open(WORK_COUNTS) as _f:
+    _WORK = json.load(_f)
+FLOPS_PER_PIECE = _WORK["tet-soup-to-256^3"]["flops_per_piece"]            # the soup
+FLOPS_PER_PIECE_LATTICE = _WORK["zeldovich-64^3-lattice-to-128^3"]["flops_per_piece"]  # deformed lattices
 PEAK_FP32_TFLOPS = 157.3
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
@@ -200,7 +203,7 @@ def batch_leg(ctx, steps, warmup, peaks=None):
         sec = row["batched"]["ms_per_step"] * 1e-3
         peak_alu = PEAK_FP32_TFLOPS if prec == "fp32c" else PEAK_FP64_TFLOPS
         apk = peaks.get(prec) if peaks else None
-        row["batched"].update({"alu_frac": pieces * FLOPS_PER_PIECE / sec / 1e12 / peak_alu,
+        row["batched"].update({"alu_frac": pieces * FLOPS_PER_PIECE_LATTICE / sec / 1e12 / peak_alu,
                                "hbm_frac": algo / sec / 1e9 / PEAK_HBM_GBS,
                                "atomic_frac": pieces / sec / apk if apk else None})
         ctx.set_tuning(*saved)
@@ -349,10 +352,11 @@ def configs_leg(ctx, steps, warmup, peaks, refined=True):
     Zel'dovich lattice onto 128^3 (1.57M tets, per-vertex densities) and the
     two-level refined 128^3 lattice onto 512^3 (50.3M tets, heavy shell
     crossing).  Per precision: time per call, pieces, error of the total mass,
-    and the three fractions -- ALU (pieces x FLOPS_PER_PIECE over the clip
-    kernel's time against the vector peak of that precision), HBM (inputs read
-    once plus the output grids written once, over the call) and atomic
-    (deposits over the clip kernel's time against the measured rate)."""
+    and the three fractions -- ALU (pieces x the lattice's counted flops per
+    piece over the clip kernel's time against the vector peak of that
+    precision), HBM (inputs read once plus the output grids written once,
+    over the call) and atomic (deposits over the clip kernel's time against
+    the measured rate)."""
     import torch
 
     from paper_1509_07720_amd import synth
@@ -404,7 +408,7 @@ def configs_leg(ctx, steps, warmup, peaks, refined=True):
             apk = peaks.get(prec) if peaks else None
             row[prec] = {"ms_per_call": sec * 1e3, "simplices_per_s": simp.shape[0] / sec, "clip_ms": clip_s * 1e3,
                          "pieces": pieces, "mass_rel_err": abs(float(total.cpu()[0]) - exact) / exact,
-                         "alu_frac": pieces * FLOPS_PER_PIECE / clip_s / 1e12 / peak_alu,
+                         "alu_frac": pieces * FLOPS_PER_PIECE_LATTICE / clip_s / 1e12 / peak_alu,
                          "hbm_frac": algo / sec / 1e9 / PEAK_HBM_GBS,
                          "atomic_frac": dep_rate / apk if apk else None, "deposits_per_s": dep_rate}
             log(f"config {name} {prec}: {sec * 1e3:.2f} ms/call, {pieces} pieces")

@@ -14,9 +14,13 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 * ``mc``             -- Monte Carlo deposit, the paper's particle-sampling
                         check (Section 5.2).
 * ``vertex_density`` -- the per-vertex density estimate (Section 4).
-* ``amr``            -- the two-stage projection: exact onto grids coarsened
-                        per simplex by its smallest height, then donor cell
-                        onto the uniform grid (Section 4).
+* ``amr``            -- the two-stage projection: exact onto an adaptive
+                        grid refined region by region until no cell is larger
+                        than the smallest height of a simplex meeting it,
+                        then donor cell onto the uniform grid (Section 4).
+* ``work``           -- work counts of the slab recursion (intersection
+                        points, classifications, fan tetrahedra) that price
+                        the projection's arithmetic.
 """
 from __future__ import annotations
 
