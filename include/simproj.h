@@ -48,6 +48,13 @@
  * such error is reported by sp_sync_status.  The context owns its
  * scratch memory; a context must not be used by two host threads at once,
  * and calls on one context must be ordered (one stream, or synchronised).
+ * Scratch grows in stream order on the call's stream (freed and allocated
+ * behind the work already enqueued there, with no device-wide wait; only a
+ * context holding captured batch launches waits for the device before it
+ * drops them).  The environment variable SP_SCRATCH_CAP (bytes, with an
+ * optional K, M or G suffix), read by sp_create, bounds the device memory a
+ * context holds; a call that would need more returns SP_E_NO_MEMORY before
+ * it enqueues anything, and the context stays usable.
  */
 #ifndef SIMPROJ_H
 #define SIMPROJ_H
@@ -67,7 +74,7 @@ typedef enum {
     SP_E_NONFINITE = 3,     /* (SP_VALIDATE) a NaN/Inf position or density */
     SP_E_PERIODIC_SPAN = 4, /* (SP_VALIDATE) a simplex spans >= extent/2 on a periodic axis,
                                or 32768 cells or more on any axis */
-    SP_E_NO_MEMORY = 5,     /* scratch allocation failed */
+    SP_E_NO_MEMORY = 5,     /* scratch allocation failed, or SP_SCRATCH_CAP exceeded */
     SP_E_DEVICE = 6,        /* no usable HIP device, or a HIP call failed */
     SP_E_UNSUPPORTED = 7,   /* valid request this build does not handle */
     SP_E_INTERNAL = 8       /* a polytope exceeded every capacity (should not happen) */
@@ -132,9 +139,10 @@ sp_status sp_project_tets(sp_ctx *ctx, const sp_problem *prob, sp_precision prec
  * lists live in a static scratch array of 128 MiB in device memory, one copy
  * per GPU the library runs on, held from the first sp_create on that device
  * until the process ends.  A problem whose work lists do not fit returns
- * SP_E_NO_MEMORY synchronously and enqueues nothing; roughly, 16 bytes per
- * simplex plus, when out_lo is NULL in FP32C mode, 4 bytes per cell, on top
- * of 26 MiB of fixed lists (about 6M tetrahedra with a caller-held out_lo).
+ * SP_E_NO_MEMORY synchronously and enqueues nothing; roughly, 136 bytes per
+ * simplex (work lists and its set-up record) plus, when out_lo is NULL in
+ * FP32C mode, 4 bytes per cell, on top of 26 MiB of fixed lists (about 780K
+ * tetrahedra with a caller-held out_lo).
  * Every call on one GPU shares that GPU's array, and a call leaves its
  * contents behind: each call writes everything it reads before reading it,
  * but calls whose work overlaps in time on one GPU (different streams or

@@ -1504,12 +1504,27 @@ constexpr int NOALLOC_MAX_DEVICES = 64;
 static void *g_noalloc_ptr[NOALLOC_MAX_DEVICES];
 static std::mutex g_noalloc_mu;
 
+// SP_SCRATCH_CAP: bytes, with an optional K, M or G suffix (powers of 1024).
+static size_t parse_bytes(const char *e)
+{
+    char *end = nullptr;
+    const double v = strtod(e, &end);
+    if (!(v > 0.0)) return 0;
+    double m = 1.0;
+    if (end && (*end == 'K' || *end == 'k')) m = 1024.0;
+    else if (end && (*end == 'M' || *end == 'm')) m = 1024.0 * 1024.0;
+    else if (end && (*end == 'G' || *end == 'g')) m = 1024.0 * 1024.0 * 1024.0;
+    return (size_t)(v * m);
+}
+
 struct sp_ctx {
     int device;
     void *noalloc;   // this device's copy of `scratch` (NULL if its address could not be taken)
     int num_cu;
     void *scratch;
     size_t scratch_cap;
+    size_t held;           // device memory held in scratch and aux buffers
+    size_t scratch_limit;  // SP_SCRATCH_CAP (0: none)
     CallState *cs;
     ErrState *es;
     double *dummy_total;
@@ -1608,6 +1623,9 @@ extern "C" sp_status sp_create(int hip_device, sp_ctx **ctx)
     c->num_cu = prop.multiProcessorCount;
     c->scratch = nullptr;
     c->scratch_cap = 0;
+    c->held = 0;
+    c->scratch_limit = 0;
+    if (const char *e = getenv("SP_SCRATCH_CAP")) c->scratch_limit = parse_bytes(e);
     void *st = nullptr;
     if (hipMalloc(&st, 4096) != hipSuccess) {
         delete c;
@@ -1657,9 +1675,12 @@ extern "C" void sp_destroy(sp_ctx *ctx)
     drop_events(ctx);
     drop_graphs(ctx);
     (void)hipStreamDestroy(ctx->cap_stream);
+    // (the stream-ordered blocks are returned on the null stream, which the
+    // device-wide synchronisation above has drained, and waited for)
     for (auto &b : ctx->aux)
-        if (b.p) (void)hipFree(b.p);
-    if (ctx->scratch) (void)hipFree(ctx->scratch);
+        if (b.p) (void)hipFreeAsync(b.p, nullptr);
+    if (ctx->scratch) (void)hipFreeAsync(ctx->scratch, nullptr);
+    (void)hipStreamSynchronize(nullptr);
     (void)hipFree(ctx->cs);
     delete ctx;
 }
@@ -1669,38 +1690,51 @@ extern "C" const char *sp_last_error(const sp_ctx *)
     return g_err.c_str();
 }
 
-static sp_status ensure_buf(sp_ctx::Buf &b, size_t bytes)
+// Device memory the context owns grows in stream order on the call's
+// stream: the old block is freed and the new one allocated behind the work
+// already enqueued there (calls on one context are ordered, so nothing else
+// still uses it), without waiting for the device.  SP_SCRATCH_CAP bounds the
+// total the context may hold; a call that needs more fails with
+// SP_E_NO_MEMORY before it enqueues anything.
+static sp_status grow(sp_ctx *ctx, void *&p, size_t &cap, size_t bytes, hipStream_t stream, const char *what)
 {
-    if (bytes <= b.cap) return SP_OK;
-    HIPCHECK(hipDeviceSynchronize());
-    if (b.p) (void)hipFree(b.p);
-    b.p = nullptr;
-    b.cap = 0;
-    const size_t want = bytes + bytes / 4;
-    if (hipMalloc(&b.p, want) != hipSuccess) {
+    const size_t others = ctx->held - cap;
+    if (ctx->scratch_limit && others + bytes > ctx->scratch_limit)
+        return fail(SP_E_NO_MEMORY, "the call needs %zu bytes of %s (%zu held elsewhere); SP_SCRATCH_CAP allows %zu",
+                    bytes, what, others, ctx->scratch_limit);
+    size_t want = bytes + bytes / 4;
+    if (ctx->scratch_limit && others + want > ctx->scratch_limit) want = ctx->scratch_limit - others;
+    if (p) (void)hipFreeAsync(p, stream);
+    p = nullptr;
+    ctx->held -= cap;
+    cap = 0;
+    if (hipMallocAsync(&p, want, stream) != hipSuccess) {
         (void)hipGetLastError();
-        return fail(SP_E_NO_MEMORY, "buffer allocation of %zu bytes failed", want);
+        p = nullptr;
+        return fail(SP_E_NO_MEMORY, "allocation of %zu bytes of %s failed", want, what);
     }
-    b.cap = want;
+    cap = want;
+    ctx->held += cap;
     return SP_OK;
 }
 
-static sp_status ensure_scratch(sp_ctx *ctx, size_t bytes)
+static sp_status ensure_buf(sp_ctx *ctx, sp_ctx::Buf &b, size_t bytes, hipStream_t stream)
+{
+    if (bytes <= b.cap) return SP_OK;
+    return grow(ctx, b.p, b.cap, bytes, stream, "buffer");
+}
+
+static sp_status ensure_scratch(sp_ctx *ctx, size_t bytes, hipStream_t stream)
 {
     if (bytes <= ctx->scratch_cap) return SP_OK;
-    HIPCHECK(hipDeviceSynchronize());
-    drop_graphs(ctx);  // captured launches refer to the old scratch
-    if (ctx->scratch) (void)hipFree(ctx->scratch);
-    ctx->scratch = nullptr;
-    ctx->scratch_cap = 0;
-    size_t want = bytes + bytes / 4;
-    if (hipMalloc(&ctx->scratch, want) != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(SP_E_NO_MEMORY, "scratch allocation of %zu bytes failed", want);
+    if (!ctx->graphs.empty()) {
+        // captured launches refer to the old scratch: let them finish, drop them
+        HIPCHECK(hipDeviceSynchronize());
+        drop_graphs(ctx);
     }
-    ctx->scratch_cap = want;
-    return SP_OK;
+    return grow(ctx, ctx->scratch, ctx->scratch_cap, bytes, stream, "scratch");
 }
+
 
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -1783,7 +1817,8 @@ template <int D, typename T>
 // that buffer of fixed_cap bytes instead of the context's, with room for
 // fewer split items, and fail when it does not fit.
 static sp_status prepare(sp_ctx *ctx, const sp_problem *probs, int n, Prepared<T> *out, int64_t &ntotal,
-                         bool batched = false, bool work_lists = true, void *fixed = nullptr, size_t fixed_cap = 0)
+                         hipStream_t stream, bool batched = false, bool work_lists = true, void *fixed = nullptr,
+                         size_t fixed_cap = 0)
 {
     const bool fp32 = sizeof(T) == 4;
     ntotal = 0;
@@ -1819,7 +1854,7 @@ static sp_status prepare(sp_ctx *ctx, const sp_problem *probs, int n, Prepared<T
                                         "entry point holds %zu", off, fixed_cap);
         base = reinterpret_cast<char *>(fixed);
     } else {
-        sp_status st = ensure_scratch(ctx, off);
+        sp_status st = ensure_scratch(ctx, off, stream);
         if (st != SP_OK) return st;
         base = reinterpret_cast<char *>(ctx->scratch);
     }
@@ -1972,7 +2007,7 @@ static sp_status project_impl(sp_ctx *ctx, const sp_problem *prob, hipStream_t s
     std::vector<Prepared<T>> v;
     int64_t ntotal = 0;
     v.resize(1);
-    sp_status st = prepare<D, T>(ctx, prob, 1, v.data(), ntotal);
+    sp_status st = prepare<D, T>(ctx, prob, 1, v.data(), ntotal, stream);
     if (st != SP_OK) return st;
     Batch b = {nullptr, nullptr, 0};
     if (ctx->profiling) ctx->prof_calls++;
@@ -2008,12 +2043,12 @@ extern "C" sp_status sp_project_tets_noalloc(sp_ctx *ctx, const sp_problem *prob
     int64_t ntotal = 0;
     if (prec == SP_PREC_FP32C) {
         Prepared<float> one;
-        st = prepare<3, float>(ctx, prob, 1, &one, ntotal, false, true, ctx->noalloc, NOALLOC_SCRATCH_BYTES);
+        st = prepare<3, float>(ctx, prob, 1, &one, ntotal, s, false, true, ctx->noalloc, NOALLOC_SCRATCH_BYTES);
         if (st != SP_OK) return st;
         enqueue<3, float>(ctx, &one, 1, b, (ntotal + 255) / 256, s, false);
     } else {
         Prepared<double> one;
-        st = prepare<3, double>(ctx, prob, 1, &one, ntotal, false, true, ctx->noalloc, NOALLOC_SCRATCH_BYTES);
+        st = prepare<3, double>(ctx, prob, 1, &one, ntotal, s, false, true, ctx->noalloc, NOALLOC_SCRATCH_BYTES);
         if (st != SP_OK) return st;
         enqueue<3, double>(ctx, &one, 1, b, (ntotal + 255) / 256, s, false);
     }
@@ -2034,7 +2069,7 @@ extern "C" sp_status sp_project_tets_corners(sp_ctx *ctx, const sp_problem *prob
     std::vector<Prepared<double>> v;
     int64_t ntotal = 0;
     v.resize(1);
-    st = prepare<3, double>(ctx, prob, 1, v.data(), ntotal, false, false);
+    st = prepare<3, double>(ctx, prob, 1, v.data(), ntotal, s, false, false);
     if (st != SP_OK) return st;
     const Prepared<double> &q = v[0];
     hipLaunchKernelGGL(k_clear_state, dim3(1), dim3(64), 0, s, ctx->cs, q.total);
@@ -2093,7 +2128,7 @@ extern "C" sp_status sp_project_tets_accurate(sp_ctx *ctx, const sp_problem *pro
     off = align_up(off + sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
     const size_t o_patch = off;
     off = align_up(off + sizeof(double) * ncell);
-    st = ensure_buf(ctx->aux[0], off);
+    st = ensure_buf(ctx, ctx->aux[0], off, s);
     if (st != SP_OK) return st;
     char *base = static_cast<char *>(ctx->aux[0].p);
     float *lo = own_lo ? reinterpret_cast<float *>(base + o_lo) : prob->out_lo;
@@ -2110,7 +2145,7 @@ extern "C" sp_status sp_project_tets_accurate(sp_ctx *ctx, const sp_problem *pro
     std::vector<Prepared<float>> v;
     int64_t ntotal = 0;
     v.resize(1);
-    st = prepare<3, float>(ctx, &p1, 1, v.data(), ntotal);
+    st = prepare<3, float>(ctx, &p1, 1, v.data(), ntotal, s);
     if (st != SP_OK) return st;
     v[0].p.cmax = cmax;
     hipLaunchKernelGGL(k_fill<uint32_t>, dim3(grid_blocks(ncell, 256)), dim3(256), 0, s, cmax, ncell);
@@ -2135,7 +2170,7 @@ extern "C" sp_status sp_project_tets_accurate(sp_ctx *ctx, const sp_problem *pro
         const size_t q_s = align_up(q_x + sizeof(double) * nx);
         const size_t q_r = align_up(q_s + sizeof(int32_t) * 4 * (size_t)ntag);
         const size_t q_end = align_up(q_r + sizeof(double) * 4 * (size_t)ntag);
-        st = ensure_buf(ctx->aux[1], q_end);
+        st = ensure_buf(ctx, ctx->aux[1], q_end, s);
         if (st != SP_OK) return st;
         char *b2 = static_cast<char *>(ctx->aux[1].p);
         double *x64 = reinterpret_cast<double *>(b2 + q_x);
@@ -2218,7 +2253,7 @@ static sp_status amr_impl(sp_ctx *ctx, const sp_problem *prob, sp_precision prec
         o_sum[l] = off;
         off = align_up(off + sizeof(T) * nblk[l]);
     }
-    sp_status st = ensure_buf(ctx->aux[1], off);
+    sp_status st = ensure_buf(ctx, ctx->aux[1], off, s);
     if (st != SP_OK) return st;
     char *base = static_cast<char *>(ctx->aux[1].p);
     uint8_t *lv = reinterpret_cast<uint8_t *>(base + o_lv);
@@ -2232,7 +2267,7 @@ static sp_status amr_impl(sp_ctx *ctx, const sp_problem *prob, sp_precision prec
     int64_t ntot = 0;
     // a descriptor of the input, for the per-simplex kernels
     v.resize(1);
-    st = prepare<3, T>(ctx, prob, 1, v.data(), ntot);
+    st = prepare<3, T>(ctx, prob, 1, v.data(), ntot, s);
     if (st != SP_OK) return st;
     const ProbDev<T> pin = v[0].p;
     unsigned hc[16] = {0}, hb[16] = {0};
@@ -2332,7 +2367,7 @@ static sp_status batch_impl(sp_ctx *ctx, const sp_problem *probs, int n, sp_prec
     std::vector<Prepared<T>> v;
     int64_t ntotal = 0;
     v.resize(n);
-    sp_status st = prepare<D, T>(ctx, probs, n, v.data(), ntotal, true);
+    sp_status st = prepare<D, T>(ctx, probs, n, v.data(), ntotal, stream, true);
     if (st != SP_OK) return st;
     uint64_t key = 1469598103934665603ull;
     const int dim = D;
@@ -2419,7 +2454,7 @@ static sp_status vertex_density_impl(sp_ctx *ctx, const void *xyz, int64_t n_ver
 {
     HIPCHECK(hipSetDevice(ctx->device));
     if (n_vert == 0) return SP_OK;
-    sp_status st = ensure_scratch(ctx, sizeof(double) * 2 * (size_t)n_vert);
+    sp_status st = ensure_scratch(ctx, sizeof(double) * 2 * (size_t)n_vert, stream);
     if (st != SP_OK) return st;
     double *acc = reinterpret_cast<double *>(ctx->scratch);
     const size_t nacc = 2 * (size_t)n_vert;

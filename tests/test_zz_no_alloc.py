@@ -72,9 +72,9 @@ def test_noalloc_matches_allocating_call_twice(prec, keep_lo):
 
 
 def test_noalloc_refuses_a_problem_beyond_its_scratch():
-    """About 6M tets fit with a caller-held low grid; 20M cannot
-    (20M simplices need over 300 MB of work lists; the check is on sizes
-    alone, before anything is enqueued)."""
+    """About 780K tets fit with a caller-held low grid; 20M cannot (20M
+    simplices need over 2 GB of work lists and set-up records; the check is
+    on sizes alone, before anything is enqueued)."""
     ctx = simproj.Context(0)
     d = torch.device("cuda:0")
     xyz = torch.zeros((4, 3), dtype=torch.float32, device=d)
