@@ -126,7 +126,8 @@ def atomic_peaks():
 def batch_leg(ctx, steps, warmup, peaks=None):
     """The batched workload: one graph launch for 64 problems against 64
     sequential calls; FP32C and FP64.  The launch parameters are tuned on the
-    64 problems first (sp_autotune with a cache file, timed separately).
+    64 problems first (sp_autotune with a cache file, timed separately; it
+    times candidates as the batched launch).
     With the pieces counted one problem at a time (untimed), the batched
     launch's ALU, HBM and atomic fractions as for the other workloads, over
     the whole launch."""
@@ -171,8 +172,8 @@ def batch_leg(ctx, steps, warmup, peaks=None):
         t = time.perf_counter()
         ctx.autotune(3, recs, precision=prec, cache_path=cache)  # found in the cache: no timing
         cached_s = time.perf_counter() - t
-        log(f"batch {prec}: autotuned slab group {tuned[0]}, blocks/CU {tuned[1]} in {tune_s:.1f}s "
-            f"(cache hit {cached_s * 1e3:.1f} ms)")
+        log(f"batch {prec}: autotuned slab group {tuned[0]}, blocks/CU {tuned[1]}, item pieces {tuned[2]} "
+            f"in {tune_s:.1f}s (cache hit {cached_s * 1e3:.1f} ms)")
         pieces = 0
         ctx.profile(2)
         for r in recs:
@@ -188,9 +189,16 @@ def batch_leg(ctx, steps, warmup, peaks=None):
         torch.cuda.synchronize()
         first = time.perf_counter() - t
         row = {"first_call_ms": first * 1e3, "pieces": pieces,
-               "autotune": {"slab_group": tuned[0], "blocks_per_cu": tuned[1], "tune_s": tune_s,
-                            "cache_hit_s": cached_s}}
+               "autotune": {"slab_group": tuned[0], "blocks_per_cu": tuned[1], "item_pieces": tuned[2],
+                            "tune_s": tune_s, "cache_hit_s": cached_s}}
         for name, fn in (("batched", batched), ("sequential", sequential)):
+            # the batched launch with the tuned parameters; the calls one by
+            # one with the default ones (the item size then follows each
+            # call's own size)
+            if name == "batched":
+                ctx.set_tuning(*tuned)
+            else:
+                ctx.set_tuning(*saved)
             for _ in range(warmup):
                 fn()
             torch.cuda.synchronize()

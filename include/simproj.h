@@ -267,30 +267,36 @@ sp_status sp_vertex_density(sp_ctx *ctx, int dim, const void *xyz, int64_t n_ver
  * the previous call (SP_VALIDATE checks, capacity failures) and clear it. */
 sp_status sp_sync_status(sp_ctx *ctx, void *stream);
 
-/* Time the tunable launch parameters (the x-slab group of a work item and
- * the clip blocks per CU) on the n sample problems of dimension `dim` and
- * keep the fastest for subsequent calls of this context.  Project-written
- * search: every candidate pair is run once to warm up and then timed twice
- * with HIP events, the sample projected one problem after another; the
- * sample's output grids are overwritten.  When cache_path is not NULL the
- * text file is searched first for a line with the sample's signature (its
- * sizes, grid descriptions, precision and CU count, not its pointers); if
- * found, its parameters are applied without timing, else the result is
- * appended to the file (SP_E_INVALID_ARG if it cannot be written; the result
- * is applied anyway).  Synchronous. */
+/* Time the tunable launch parameters (the x-slab group of a work item, the
+ * expected pieces a big simplex's work items are cut down to, and the clip
+ * blocks per CU) on the n sample problems of dimension `dim` and keep the
+ * fastest for subsequent calls of this context (the cost-based balancing of
+ * the work items, Section 7).  The sample is timed in the form it is tuned
+ * for: one problem by itself, several as one sp_project_batch launch.
+ * Search: coordinate descent from the parameters in use, each parameter in
+ * turn over its candidates with the others held, twice round; every
+ * candidate is run once to warm up and then timed twice with HIP events.
+ * The sample's output grids are overwritten.  When cache_path is not NULL
+ * the text file is searched first for a line with the sample's signature
+ * (its sizes, grid descriptions, precision and CU count, not its pointers);
+ * if found, its parameters are applied without timing, else the result is
+ * appended to the file (SP_E_INVALID_ARG if it cannot be written; the
+ * result is applied anyway).  Synchronous. */
 sp_status sp_autotune(sp_ctx *ctx, int dim, const sp_problem *sample, int n, sp_precision prec,
                       const char *cache_path);
 
-/* The launch parameters in use: the most x-slabs per work item and clip
- * blocks per CU (0: as many as fit on a CU).  Either pointer may be NULL.
- * (A big simplex is cut into work items of fewer slabs, each of about one
- * lane's expected share of the launch's pieces; the slab group caps that.) */
-sp_status sp_tuning_read(sp_ctx *ctx, int *slab_group, int *blocks_per_cu);
+/* The launch parameters in use: the most x-slabs per work item, clip blocks
+ * per CU (0: as many as fit on a CU) and the expected pieces per work item
+ * of a big simplex (0: about one lane's share of the launch's pieces).  Any
+ * pointer may be NULL.  (A big simplex is cut into work items of fewer
+ * slabs, each of about that many expected pieces; the slab group caps it.) */
+sp_status sp_tuning_read(sp_ctx *ctx, int *slab_group, int *blocks_per_cu, int *item_pieces);
 
 /* Set the launch parameters by hand (slab_group in 1..4095, blocks_per_cu
- * in 0..64, else SP_E_INVALID_ARG); they hold for later calls of this
- * context until changed or retuned.  Results do not depend on them. */
-sp_status sp_tuning_set(sp_ctx *ctx, int slab_group, int blocks_per_cu);
+ * in 0..64, item_pieces in 0..65536, else SP_E_INVALID_ARG); they hold for
+ * later calls of this context until changed or retuned.  Results do not
+ * depend on them. */
+sp_status sp_tuning_set(sp_ctx *ctx, int slab_group, int blocks_per_cu, int item_pieces);
 
 /* Per-stage device times of the projection calls made while profiling is
  * on, from HIP events recorded on each call's own stream around its kernels

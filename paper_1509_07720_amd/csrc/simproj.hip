@@ -1830,9 +1830,10 @@ static sp_status prepare(sp_ctx *ctx, const sp_problem *probs, int n, Prepared<T
         if (fp32 && !probs[i].out_lo) lo_cells += nc;
     }
     if (ntotal >= ((int64_t)1 << 31)) return fail(SP_E_INVALID_ARG, "%lld simplices in one launch (limit 2^31)", (long long)ntotal);
-    // room for the split items: half the simplices plus 2M (16 MB), enough
-    // for ~1.3e8 pieces of big simplices at the default item size
-    const unsigned extra_cap = (unsigned)(ntotal / 2 + (fixed ? (1 << 18) : (1 << 21)));
+    // room for the split items: as many again as the simplices plus 2M
+    // (16 MB); the no-allocation scratch holds half the simplices plus 256K.
+    // A block whose split items do not fit keeps its simplices whole.
+    const unsigned extra_cap = (unsigned)(fixed ? ntotal / 2 + (1 << 18) : ntotal + (1 << 21));
     const size_t nitems = work_lists ? (size_t)ntotal + extra_cap : 0;
     size_t off = 0;
     const size_t o_tinfo = off;
@@ -2576,11 +2577,13 @@ extern "C" sp_status sp_profile_read(sp_ctx *ctx, sp_profile *out)
     return SP_OK;
 }
 
-// Launch parameters the autotuner searches: the slab group (how many
-// x-slabs one work item covers) and the clip blocks per CU (0 = as many as
-// fit).
-static const int kTuneSlab[] = {1, 2, 4, 8, 16, 32};
-static const int kTuneBlocks[] = {0, 16};
+// Launch parameters the autotuner searches: the slab group (at most how
+// many x-slabs one work item covers), the expected pieces a big simplex's
+// work items are cut down to (0: from the launch size) and the clip blocks
+// per CU (0: as many as fit).
+static const int kTuneSlab[] = {1, 2, 4, 8, 16, 32, 64};
+static const int kTuneItem[] = {0, 32, 128, 512, 2048};
+static const int kTuneBlocks[] = {0, 4, 8};
 
 // Signature of a tuning sample: what determines the best parameters, not
 // where the buffers live.
@@ -2598,6 +2601,8 @@ static uint64_t sample_signature(int dim, const sp_problem *sample, int n, sp_pr
     return h;
 }
 
+// The cache: one line per tuned sample, the last matching line wins.
+// Version 1 lines (no item size) are read with the automatic item size.
 static bool cache_lookup(const char *path, uint64_t sig, Tuning &t)
 {
     FILE *f = fopen(path, "r");
@@ -2606,11 +2611,14 @@ static bool cache_lookup(const char *path, uint64_t sig, Tuning &t)
     bool found = false;
     while (fgets(line, sizeof line, f)) {
         unsigned long long k = 0;
-        int g = 0, c = 0;
-        if (sscanf(line, "simproj-tune 1 sig=%llx slab_group=%d blocks_per_cu=%d", &k, &g, &c) == 3 && k == sig &&
-            g > 0 && g <= 4095 && c >= 0) {
+        int g = 0, c = 0, ip = 0;
+        const bool v2 = sscanf(line, "simproj-tune 2 sig=%llx slab_group=%d blocks_per_cu=%d item_pieces=%d", &k, &g,
+                               &c, &ip) == 4;
+        const bool v1 = !v2 && sscanf(line, "simproj-tune 1 sig=%llx slab_group=%d blocks_per_cu=%d", &k, &g, &c) == 3;
+        if ((v1 || v2) && k == sig && g > 0 && g <= 4095 && c >= 0 && c <= 64 && ip >= 0 && ip <= 65536) {
             t.slab_group = g;
             t.chunks_per_cu = c;
+            t.item_pieces = v2 ? ip : 0;
             found = true;
         }
     }
@@ -2641,33 +2649,61 @@ extern "C" sp_status sp_autotune(sp_ctx *ctx, int dim, const sp_problem *sample,
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIPCHECK(hipEventCreate(&e0));
     HIPCHECK(hipEventCreate(&e1));
-    float best_ms = 1e30f;
     sp_status st = SP_OK;
-    for (int g : kTuneSlab) {
-        for (int c : kTuneBlocks) {
-            ctx->tune.slab_group = g;
-            ctx->tune.chunks_per_cu = c;
-            float ms = 0.f;
-            for (int rep = 0; rep < 3 && st == SP_OK; ++rep) {  // one warm-up, then the best of two
-                (void)hipEventRecord(e0, s);
-                for (int i = 0; i < n && st == SP_OK; ++i)
-                    st = dim == 3 ? (prec == SP_PREC_FP32C ? project_impl<3, float>(ctx, &sample[i], s)
-                                                           : project_impl<3, double>(ctx, &sample[i], s))
-                                  : (prec == SP_PREC_FP32C ? project_impl<2, float>(ctx, &sample[i], s)
-                                                           : project_impl<2, double>(ctx, &sample[i], s));
-                (void)hipEventRecord(e1, s);
-                if (hipEventSynchronize(e1) != hipSuccess) st = fail(SP_E_DEVICE, "autotune run failed");
-                float t = 0.f;
-                (void)hipEventElapsedTime(&t, e0, e1);
-                if (rep == 1 || (rep == 2 && t < ms)) ms = t;
-            }
-            if (st != SP_OK) break;
-            if (ms < best_ms) {
-                best_ms = ms;
-                best = ctx->tune;
+    // one sample run: a single problem by itself, several as one batched
+    // launch (the form they are tuned for)
+    auto run = [&]() -> sp_status {
+        if (n > 1) {
+            if (dim == 3)
+                return prec == SP_PREC_FP32C ? batch_impl<3, float>(ctx, sample, n, prec, s)
+                                             : batch_impl<3, double>(ctx, sample, n, prec, s);
+            return prec == SP_PREC_FP32C ? batch_impl<2, float>(ctx, sample, n, prec, s)
+                                         : batch_impl<2, double>(ctx, sample, n, prec, s);
+        }
+        if (dim == 3)
+            return prec == SP_PREC_FP32C ? project_impl<3, float>(ctx, sample, s) : project_impl<3, double>(ctx, sample, s);
+        return prec == SP_PREC_FP32C ? project_impl<2, float>(ctx, sample, s) : project_impl<2, double>(ctx, sample, s);
+    };
+    // time of the current parameters: one warm-up run (it also captures a
+    // batched launch), then the best of two
+    auto timed = [&](float &ms) -> sp_status {
+        ms = 1e30f;
+        for (int rep = 0; rep < 3; ++rep) {
+            (void)hipEventRecord(e0, s);
+            sp_status r = run();
+            if (r != SP_OK) return r;
+            (void)hipEventRecord(e1, s);
+            if (hipEventSynchronize(e1) != hipSuccess) return fail(SP_E_DEVICE, "autotune run failed");
+            float t = 0.f;
+            (void)hipEventElapsedTime(&t, e0, e1);
+            if (rep > 0 && t < ms) ms = t;
+        }
+        return SP_OK;
+    };
+    // coordinate descent from the current parameters: each parameter in turn
+    // over its candidates with the others held, twice round
+    float best_ms = 0.f;
+    st = timed(best_ms);
+    for (int pass = 0; pass < 2 && st == SP_OK; ++pass) {
+        for (int which = 0; which < 3 && st == SP_OK; ++which) {
+            const int *cand = which == 0 ? kTuneSlab : (which == 1 ? kTuneItem : kTuneBlocks);
+            const int nc = which == 0 ? (int)(sizeof kTuneSlab / sizeof(int))
+                                      : (which == 1 ? (int)(sizeof kTuneItem / sizeof(int))
+                                                    : (int)(sizeof kTuneBlocks / sizeof(int)));
+            for (int k = 0; k < nc && st == SP_OK; ++k) {
+                Tuning t = best;
+                int &field = which == 0 ? t.slab_group : (which == 1 ? t.item_pieces : t.chunks_per_cu);
+                if (field == cand[k]) continue;
+                field = cand[k];
+                ctx->tune = t;
+                float ms = 0.f;
+                st = timed(ms);
+                if (st == SP_OK && ms < best_ms) {
+                    best_ms = ms;
+                    best = t;
+                }
             }
         }
-        if (st != SP_OK) break;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -2677,28 +2713,32 @@ extern "C" sp_status sp_autotune(sp_ctx *ctx, int dim, const sp_problem *sample,
     if (cache_path) {
         FILE *f = fopen(cache_path, "a");
         if (!f) return fail(SP_E_INVALID_ARG, "cannot write the tuning cache %s", cache_path);
-        fprintf(f, "simproj-tune 1 sig=%llx slab_group=%d blocks_per_cu=%d ms=%.4f\n", (unsigned long long)sig,
-                best.slab_group, best.chunks_per_cu, best_ms);
+        fprintf(f, "simproj-tune 2 sig=%llx slab_group=%d blocks_per_cu=%d item_pieces=%d ms=%.4f\n",
+                (unsigned long long)sig, best.slab_group, best.chunks_per_cu, best.item_pieces, best_ms);
         fclose(f);
     }
     return SP_OK;
 }
 
-extern "C" sp_status sp_tuning_set(sp_ctx *ctx, int slab_group, int blocks_per_cu)
+extern "C" sp_status sp_tuning_set(sp_ctx *ctx, int slab_group, int blocks_per_cu, int item_pieces)
 {
     if (!ctx) return fail(SP_E_INVALID_ARG, "ctx is NULL");
     if (slab_group < 1 || slab_group > 4095) return fail(SP_E_INVALID_ARG, "slab_group %d not in 1..4095", slab_group);
     if (blocks_per_cu < 0 || blocks_per_cu > 64)
         return fail(SP_E_INVALID_ARG, "blocks_per_cu %d not in 0..64", blocks_per_cu);
+    if (item_pieces < 0 || item_pieces > 65536)
+        return fail(SP_E_INVALID_ARG, "item_pieces %d not in 0..65536", item_pieces);
     ctx->tune.slab_group = slab_group;
     ctx->tune.chunks_per_cu = blocks_per_cu;
+    ctx->tune.item_pieces = item_pieces;
     return SP_OK;
 }
 
-extern "C" sp_status sp_tuning_read(sp_ctx *ctx, int *slab_group, int *blocks_per_cu)
+extern "C" sp_status sp_tuning_read(sp_ctx *ctx, int *slab_group, int *blocks_per_cu, int *item_pieces)
 {
     if (!ctx) return fail(SP_E_INVALID_ARG, "ctx is NULL");
     if (slab_group) *slab_group = ctx->tune.slab_group;
     if (blocks_per_cu) *blocks_per_cu = ctx->tune.chunks_per_cu;
+    if (item_pieces) *item_pieces = ctx->tune.item_pieces;
     return SP_OK;
 }

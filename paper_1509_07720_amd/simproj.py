@@ -90,9 +90,10 @@ _lib.sp_sync_status.restype = ctypes.c_int
 _lib.sp_autotune.argtypes = [_V, ctypes.c_int, ctypes.POINTER(sp_problem), ctypes.c_int, ctypes.c_int,
                              ctypes.c_char_p]
 _lib.sp_autotune.restype = ctypes.c_int
-_lib.sp_tuning_read.argtypes = [_V, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+_lib.sp_tuning_read.argtypes = [_V, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                ctypes.POINTER(ctypes.c_int)]
 _lib.sp_tuning_read.restype = ctypes.c_int
-_lib.sp_tuning_set.argtypes = [_V, ctypes.c_int, ctypes.c_int]
+_lib.sp_tuning_set.argtypes = [_V, ctypes.c_int, ctypes.c_int, ctypes.c_int]
 _lib.sp_tuning_set.restype = ctypes.c_int
 _lib.sp_vertex_density.argtypes = [_V, ctypes.c_int, _V, ctypes.c_int64, _V, ctypes.c_int64, _V, ctypes.c_double,
                                    ctypes.POINTER(sp_grid), _V, ctypes.c_int, _V]
@@ -181,13 +182,13 @@ def sp_vertex_density(ctx, dim: int, xyz, n_vert: int, simplices, n_simplex: int
 
 
 def sp_tuning_read(ctx):
-    g, c = ctypes.c_int(), ctypes.c_int()
-    st = _lib.sp_tuning_read(ctx, ctypes.byref(g), ctypes.byref(c))
-    return st, g.value, c.value
+    g, c, ip = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    st = _lib.sp_tuning_read(ctx, ctypes.byref(g), ctypes.byref(c), ctypes.byref(ip))
+    return st, g.value, c.value, ip.value
 
 
-def sp_tuning_set(ctx, slab_group: int, blocks_per_cu: int) -> int:
-    return _lib.sp_tuning_set(ctx, int(slab_group), int(blocks_per_cu))
+def sp_tuning_set(ctx, slab_group: int, blocks_per_cu: int, item_pieces: int = 0) -> int:
+    return _lib.sp_tuning_set(ctx, int(slab_group), int(blocks_per_cu), int(item_pieces))
 
 
 def sp_profile_enable(ctx, on: int) -> int:
@@ -407,19 +408,21 @@ class Context:
         _check(sp_project_batch(self.handle, dim, list(problems), prec, _stream_ptr(stream)), "sp_project_batch")
 
     def autotune(self, dim: int, sample, precision: str = "fp32c", cache_path: Optional[str] = None):
-        """Tune the launch parameters on sample problems; returns
-        (slab_group, blocks_per_cu) now in use."""
+        """Tune the launch parameters on sample problems (several are timed
+        as one batched launch); returns (slab_group, blocks_per_cu,
+        item_pieces) now in use."""
         prec = SP_PREC_FP32C if precision == "fp32c" else SP_PREC_FP64
         _check(sp_autotune(self.handle, dim, list(sample), prec, cache_path), "sp_autotune")
         return self.tuning()
 
-    def set_tuning(self, slab_group: int, blocks_per_cu: int = 0) -> None:
-        _check(sp_tuning_set(self.handle, slab_group, blocks_per_cu), "sp_tuning_set")
+    def set_tuning(self, slab_group: int, blocks_per_cu: int = 0, item_pieces: int = 0) -> None:
+        _check(sp_tuning_set(self.handle, slab_group, blocks_per_cu, item_pieces), "sp_tuning_set")
 
     def tuning(self):
-        st, g, c = sp_tuning_read(self.handle)
+        """(slab_group, blocks_per_cu, item_pieces) in use."""
+        st, g, c, ip = sp_tuning_read(self.handle)
         _check(st, "sp_tuning_read")
-        return g, c
+        return g, c, ip
 
     def sync_status(self, stream=None) -> int:
         return sp_sync_status(self.handle, _stream_ptr(stream))

@@ -197,13 +197,13 @@ def test_batch_2d(ctx, prec):
         _assert_parity(d.grid(), oracle.project(p), prec, f"2d problem {i}")
 
 
-@pytest.mark.parametrize("slab_group, blocks", [(1, 0), (2, 4), (16, 0), (4, 1)])
-def test_results_independent_of_launch_parameters(ctx, slab_group, blocks):
+@pytest.mark.parametrize("slab_group, blocks, item_pieces", [(1, 0, 0), (2, 4, 32), (16, 0, 2048), (4, 1, 128)])
+def test_results_independent_of_launch_parameters(ctx, slab_group, blocks, item_pieces):
     prec = "fp32c"
     prob = synth.as_float32(synth.tet_soup(n_tets=20000, grid=256, seed=3))
     old = ctx.tuning()
     try:
-        ctx.set_tuning(slab_group, blocks)
+        ctx.set_tuning(slab_group, blocks, item_pieces)
         d = Dev(prob, prec)
         st = simproj.sp_project_tets(ctx.handle, d.rec, simproj.SP_PREC_FP32C, simproj._stream_ptr(None))
         assert st == simproj.SP_OK
@@ -214,28 +214,60 @@ def test_results_independent_of_launch_parameters(ctx, slab_group, blocks):
 
 
 def test_tuning_set_rejects_out_of_range(ctx):
-    assert simproj.sp_tuning_set(ctx.handle, 0, 0) == simproj.SP_E_INVALID_ARG
-    assert simproj.sp_tuning_set(ctx.handle, 4, 65) == simproj.SP_E_INVALID_ARG
+    assert simproj.sp_tuning_set(ctx.handle, 0, 0, 0) == simproj.SP_E_INVALID_ARG
+    assert simproj.sp_tuning_set(ctx.handle, 4, 65, 0) == simproj.SP_E_INVALID_ARG
+    assert simproj.sp_tuning_set(ctx.handle, 4, 0, -1) == simproj.SP_E_INVALID_ARG
+    assert simproj.sp_tuning_set(ctx.handle, 4, 0, 65537) == simproj.SP_E_INVALID_ARG
 
 
-def test_autotune_picks_candidate_and_caches(ctx, tmp_path):
+@pytest.mark.parametrize("batched", [False, True])
+def test_autotune_picks_candidate_and_caches(ctx, tmp_path, batched):
+    """One problem is tuned by itself, two as a batched launch; the result
+    is one of the candidates, is written to the cache and read back from it
+    without timing, and leaves the projection exact."""
     prec = "fp32c"
-    prob = synth.as_float32(synth.zeldovich_3d(n=24, grid=48, sigma_cells=1.5, seed=7))
+    probs = [synth.as_float32(synth.zeldovich_3d(n=24, grid=48, sigma_cells=1.5, seed=7))]
+    if batched:
+        probs.append(synth.as_float32(synth.zeldovich_3d(n=16, grid=64, sigma_cells=2.0, seed=8)))
+    devs = [Dev(p, prec) for p in probs]
+    cache = str(tmp_path / "tune.txt")
+    old = ctx.tuning()
+    try:
+        g, c, ip = ctx.autotune(3, [d.rec for d in devs], precision=prec, cache_path=cache)
+        assert g in (1, 2, 4, 8, 16, 32, 64) and c in (0, 4, 8) and ip in (0, 32, 128, 512, 2048)
+        lines = open(cache).read().splitlines()
+        assert len(lines) == 1 and lines[0].startswith("simproj-tune 2 sig=")
+        ctx.set_tuning(3, 2, 77)
+        assert ctx.autotune(3, [d.rec for d in devs], precision=prec, cache_path=cache) == (g, c, ip)  # cached
+        assert len(open(cache).read().splitlines()) == 1
+        if batched:
+            st = simproj.sp_project_batch(ctx.handle, 3, [d.rec for d in devs], simproj.SP_PREC_FP32C,
+                                          simproj._stream_ptr(None))
+        else:
+            st = simproj.sp_project_tets(ctx.handle, devs[0].rec, simproj.SP_PREC_FP32C, simproj._stream_ptr(None))
+        assert st == simproj.SP_OK
+        assert ctx.sync_status() == simproj.SP_OK
+        for i, (p, d) in enumerate(zip(probs, devs)):
+            _assert_parity(d.grid(), _ref(p, prec), prec, f"after autotune, problem {i}")
+    finally:
+        ctx.set_tuning(*old)
+
+
+def test_autotune_reads_version_1_cache_lines(ctx, tmp_path):
+    """A cache written before the item size was tuned is still honoured
+    (its line carries no item size: the automatic one is used)."""
+    prec = "fp32c"
+    prob = synth.as_float32(synth.zeldovich_3d(n=12, grid=32, sigma_cells=1.5, seed=9))
     d = Dev(prob, prec)
     cache = str(tmp_path / "tune.txt")
     old = ctx.tuning()
     try:
-        g, c = ctx.autotune(3, [d.rec], precision=prec, cache_path=cache)
-        assert g in (1, 2, 4, 8, 16, 32) and c in (0, 16)
-        lines = open(cache).read().splitlines()
-        assert len(lines) == 1 and lines[0].startswith("simproj-tune 1 sig=")
-        ctx.set_tuning(3, 2)
-        assert ctx.autotune(3, [d.rec], precision=prec, cache_path=cache) == (g, c)  # read back, not re-timed
-        assert len(open(cache).read().splitlines()) == 1
-        st = simproj.sp_project_tets(ctx.handle, d.rec, simproj.SP_PREC_FP32C, simproj._stream_ptr(None))
-        assert st == simproj.SP_OK
-        assert ctx.sync_status() == simproj.SP_OK
-        _assert_parity(d.grid(), _ref(prob, prec), prec, "after autotune")
+        ctx.autotune(3, [d.rec], precision=prec, cache_path=cache)
+        sig = open(cache).read().split()[2]
+        with open(cache, "w") as f:
+            f.write(f"simproj-tune 1 {sig} slab_group=8 blocks_per_cu=4 ms=1.0\n")
+        ctx.set_tuning(1, 0, 512)
+        assert ctx.autotune(3, [d.rec], precision=prec, cache_path=cache) == (8, 4, 0)
     finally:
         ctx.set_tuning(*old)
 
