@@ -469,27 +469,30 @@ struct Poly3 {
         bool open = false, ba = false;
         S4<T> a;
         T e0x = 0, e0y = 0, e0z = 0, epx = 0, epy = 0, epz = 0, rf = 0, rp = 0;
-        auto acc = [&](const S4<T> &q) {
+        // one point of the facet polygon, if valid: the fan triangle it
+        // closes with the first and the previous point.  Straight-line code
+        // with selects (every lane of a wave runs it whether its point is
+        // valid or not), so that the walk carries no nested branches.
+        auto acc = [&](const S4<T> &q, bool valid) {
             const T ex = q.x - A.x, ey = q.y - A.y, ez = q.z - A.z;
             const T rq = clamp_rho(rA + (g[0] * ex + g[1] * ey + g[2] * ez));
-            if (cnt == 0) {
-                e0x = ex;
-                e0y = ey;
-                e0z = ez;
-                rf = rq;
-            } else if (cnt >= 2) {
-                const T cx = ey * epz - ez * epy;
-                const T cy = ez * epx - ex * epz;
-                const T cz = ex * epy - ey * epx;
-                const T d = e0x * cx + e0y * cy + e0z * cz;
-                s6 += d;
-                s24 += d * (rA + rf + rp + rq);
-            }
-            epx = ex;
-            epy = ey;
-            epz = ez;
-            rp = rq;
-            ++cnt;
+            const T cx = ey * epz - ez * epy;
+            const T cy = ez * epx - ex * epz;
+            const T cz = ex * epy - ey * epx;
+            const T d = e0x * cx + e0y * cy + e0z * cz;
+            const bool tri = valid && cnt >= 2;
+            s6 += tri ? d : T(0);
+            s24 += tri ? d * (rA + rf + rp + rq) : T(0);
+            const bool first = valid && cnt == 0;
+            e0x = first ? ex : e0x;
+            e0y = first ? ey : e0y;
+            e0z = first ? ez : e0z;
+            rf = first ? rq : rf;
+            epx = valid ? ex : epx;
+            epy = valid ? ey : epy;
+            epz = valid ? ez : epz;
+            rp = valid ? rq : rp;
+            cnt += valid ? 1 : 0;
         };
         const int steps = 3 * __builtin_popcount(live);
         for (int it = 0; it < steps; ++it) {
@@ -516,18 +519,24 @@ struct Poly3 {
             const S4<T> b = V(vnext);
             const uint32_t nnext = (uint32_t)b.nb;
             const bool bb = (below >> vnext) & 1u;
-            if (ba) acc(a);
-            if (ba != bb) acc(ba ? isect3(a, b, ax, c) : isect3(b, a, ax, c));
-            if (vnext == vs) {
-                open = false;
-            } else {
-                const int np = slot_of(nnext, vcur);
-                pc = (np + 1) % 3;
-                vcur = vnext;
-                a = b;
-                ncur = nnext;
-                ba = bb;
-            }
+            acc(a, ba);
+            // the crossing point of an edge across the plane, always from its
+            // lower end; unused (and possibly not finite) on other edges
+            S4<T> lo, hi;  // (selected by value: a conditional reference would go to scratch memory)
+            lo.x = ba ? a.x : b.x;
+            lo.y = ba ? a.y : b.y;
+            lo.z = ba ? a.z : b.z;
+            hi.x = ba ? b.x : a.x;
+            hi.y = ba ? b.y : a.y;
+            hi.z = ba ? b.z : a.z;
+            acc(isect3(lo, hi, ax, c), ba != bb);
+            open = vnext != vs;
+            const int np = slot_of(nnext, vcur);
+            pc = np == 2 ? 0 : np + 1;
+            vcur = vnext;
+            a = b;
+            ncur = nnext;
+            ba = bb;
         }
         return !open && ((un0 | un1 | un2) & below) == 0u;
     }
