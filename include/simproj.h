@@ -210,18 +210,21 @@ sp_status sp_project_tets_amr(sp_ctx *ctx, const sp_problem *prob, sp_precision 
  * simplex).  Every vertex of every piece adds its terms to its cell; no
  * piece is built.  The same result as sp_project_tets in FP64 mode, by the
  * paper's own formulation, for comparison of speed and accuracy; the terms
- * are signed and cancel within a cell (tested to 1e-10 of the cell's
- * coverage scale, 1e-12 of the total on meshes in general position).
+ * are signed and cancel within a cell (tested to 1e-12 of the cell's
+ * coverage scale and of the total, degenerate meshes included).
  *   prob   as for sp_project_tets, with xyz, rho and out in double
- * Predicates are evaluated in FP64 and need general position with respect
- * to the grid: a simplex with a corner on a grid plane (lattice-aligned
- * meshes, FP32 inputs) is moved with its density by a generic offset of
- * about 1e-12 cells, which changes its pieces by about that fraction of a
- * cell and its total not at all; a facet through a grid point or a grid
- * line through a facet's boundary that remains is summed anyway and
- * reported by sp_sync_status as SP_E_UNSUPPORTED (count in the message).
- * A simplex whose bounding box holds more than 2^24 cells is skipped and
- * reported the same way (one thread enumerates its cells). */
+ * Degenerate positions with respect to the grid (corners on grid planes,
+ * lines or points, edges or facets through grid lines or points, as on
+ * lattice-aligned meshes and FP32 inputs) are resolved by simulation of
+ * simplicity (Section 3.3, eq. eq_sos; App. E.1 and E.3): the grid is
+ * perturbed symbolically and each predicate that is exactly zero takes the
+ * sign of its first non-zero perturbation term.  Predicates are filtered:
+ * FP64 decides unless its value is within its rounding bound, then a
+ * double-double evaluation on the exact differences decides or declares
+ * the tie (exact for inputs with up to about 26 significant bits in cell
+ * units).  A simplex whose bounding box holds more than 2^24 cells is
+ * skipped and reported by sp_sync_status as SP_E_UNSUPPORTED (one thread
+ * enumerates its cells). */
 sp_status sp_project_tets_corners(sp_ctx *ctx, const sp_problem *prob, void *stream);
 
 /* Project n independent problems of dimension `dim` (2 or 3; 1 <= n <=

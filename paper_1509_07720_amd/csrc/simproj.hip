@@ -90,7 +90,7 @@ struct ErrState {
     int n_bad_span;
     int n_overflow;
     int n_internal;
-    int n_degenerate;  // corner sums: configurations outside general position
+    int n_degenerate;  // corner sums: simplices not summed (bounding box over 2^24 cells)
 };
 
 struct Ovf {
@@ -150,19 +150,11 @@ struct DepF32 {
 
     __device__ void operator()(int ix, int iy, int iz, float v)
     {
+#pragma clang fp contract(off)
         if (ix == suppress_ix && (iy < suppress_iy || (iy == suppress_iy && iz < suppress_iz))) return;
         ++count;
-        // periodic anchors are reduced to [0, dims) and spans are at most
-        // dims, so one conditional subtraction wraps a periodic index
-        int c[3] = {anchor[0] + ix, anchor[1] + iy, anchor[2] + iz};
-        for (int d = 0; d < 3; ++d) {
-            if (periodic[d]) {
-                c[d] = c[d] >= dims[d] ? c[d] - dims[d] : c[d];
-            } else if ((unsigned)c[d] >= (unsigned)dims[d]) {
-                return;
-            }
-        }
-        size_t idx = (size_t)c[0] * stride[0] + (size_t)c[1] * stride[1] + (size_t)c[2] * stride[2];
+        size_t idx;
+        if (!cell(ix, iy, iz, idx)) return;
         float x = v * scale;
         if (cmax) atomicMax(cmax + idx, __float_as_uint(fabsf(x)));
         float old = unsafeAtomicAdd(hi + idx, x);
@@ -177,10 +169,13 @@ struct DepF32 {
     // contributions to one cell first.
     __device__ bool cell(int ix, int iy, int iz, size_t &idx) const
     {
+        // periodic anchors are reduced to [0, dims) and local indices lie
+        // within a span of at most half the box (one below it at worst), so
+        // one conditional step wraps a periodic index
         int c[3] = {anchor[0] + ix, anchor[1] + iy, anchor[2] + iz};
         for (int d = 0; d < 3; ++d) {
             if (periodic[d]) {
-                c[d] = c[d] >= dims[d] ? c[d] - dims[d] : c[d];
+                c[d] = c[d] >= dims[d] ? c[d] - dims[d] : (c[d] < 0 ? c[d] + dims[d] : c[d]);
             } else if ((unsigned)c[d] >= (unsigned)dims[d]) {
                 return false;
             }
@@ -190,6 +185,7 @@ struct DepF32 {
     }
     __device__ void add(size_t idx, double v) const
     {
+#pragma clang fp contract(off)
         // the FP64 value as a float and the float remainder: the remainder
         // joins the low grid with the rounding error of the high sum
         const double w = v * (double)scale;
@@ -218,12 +214,13 @@ struct DepF64 {
     {
         if (ix == suppress_ix && (iy < suppress_iy || (iy == suppress_iy && iz < suppress_iz))) return;
         ++count;
-        // periodic anchors are reduced to [0, dims) and spans are at most
-        // dims, so one conditional subtraction wraps a periodic index
+        // periodic anchors are reduced to [0, dims) and local indices lie
+        // within a span of at most half the box (one below it at worst), so
+        // one conditional step wraps a periodic index
         int c[3] = {anchor[0] + ix, anchor[1] + iy, anchor[2] + iz};
         for (int d = 0; d < 3; ++d) {
             if (periodic[d]) {
-                c[d] = c[d] >= dims[d] ? c[d] - dims[d] : c[d];
+                c[d] = c[d] >= dims[d] ? c[d] - dims[d] : (c[d] < 0 ? c[d] + dims[d] : c[d]);
             } else if ((unsigned)c[d] >= (unsigned)dims[d]) {
                 return;
             }
@@ -237,7 +234,7 @@ struct DepF64 {
         int c[3] = {anchor[0] + ix, anchor[1] + iy, anchor[2] + iz};
         for (int d = 0; d < 3; ++d) {
             if (periodic[d]) {
-                c[d] = c[d] >= dims[d] ? c[d] - dims[d] : c[d];
+                c[d] = c[d] >= dims[d] ? c[d] - dims[d] : (c[d] < 0 ? c[d] + dims[d] : c[d]);
             } else if ((unsigned)c[d] >= (unsigned)dims[d]) {
                 return false;
             }
@@ -2518,7 +2515,7 @@ extern "C" sp_status sp_sync_status(sp_ctx *ctx, void *stream)
     if (e.first != 0) {
         return fail((sp_status)e.first,
                     "device errors: %d bad index, %d non-finite, %d periodic span, %d internal (%d overflow retries), "
-                    "%d simplices outside general position (corner sums)",
+                    "%d simplices too large for the corner sums",
                     e.n_bad_index, e.n_nonfinite, e.n_bad_span, e.n_internal, e.n_overflow, e.n_degenerate);
     }
     return SP_OK;

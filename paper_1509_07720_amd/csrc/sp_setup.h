@@ -87,6 +87,9 @@ struct Local {
 // & Oishi 2005).
 SP_HD inline void cell_split(float x, float o_hi, float o_lo, float s_hi, float s_lo, int &k, float &f)
 {
+    // (the product p must stay rounded where it is added: no multiply-add
+    // contraction, or its rounding error would count twice)
+#pragma clang fp contract(off)
     float dh = x - o_hi;
     float t = dh - x;
     float dl = (x - (dh - t)) + (-o_hi - t);

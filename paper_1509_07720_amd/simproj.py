@@ -263,12 +263,12 @@ class Context:
             sp_destroy(self.handle)
             self.handle = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # At interpreter shutdown the module globals this needs may already
-        # be gone; the default contexts are closed by the atexit hook below
-        # while everything is still alive, and the process end releases the
-        # rest.
-        if sys.is_finalizing():
+        # be gone (even `sys`, hence the bound default argument); the default
+        # contexts are closed by the atexit hook below while everything is
+        # still alive, and the process end releases the rest.
+        if _finalizing():
             return
         try:
             self.close()

@@ -14,10 +14,11 @@ if not torch.cuda.is_available():
     pytest.skip("no GPU", allow_module_level=True)
 
 from paper_1509_07720_amd import simproj  # noqa: E402
+from test_host_corner import half_cell_soup, snapped  # noqa: E402  (input builders only)
 
 # signed corner terms cancel within a cell: per cell relative to the
 # coverage scale, and of the total (the clipping path holds 1e-12 for both)
-TOL_CELL, TOL_MASS = 1e-10, 1e-12
+TOL_CELL, TOL_MASS = 1e-12, 1e-12
 
 
 @pytest.fixture(scope="module")
@@ -47,6 +48,9 @@ CASES = {
     "undisplaced_lattice": lambda: synth.zeldovich_3d(n=8, grid=16, sigma_cells=0.0, seed=1),
     # stretched over a non-periodic box: wrapped simplices span it, parts fall outside
     "non_periodic": lambda: stretched(synth.zeldovich_3d(n=8, grid=16, sigma_cells=1.0, seed=8)),
+    # degenerate positions resolved by simulation of simplicity
+    "quarter_cell_lattice": lambda: snapped(synth.zeldovich_3d(n=8, grid=16, sigma_cells=1.0, seed=4), 4),
+    "half_cell_soup": lambda: half_cell_soup(400, 12, seed=7),
 }
 
 
@@ -66,17 +70,23 @@ def test_corners_match_oracle(ctx, name):
 
 def test_corners_agree_with_clipping_at_full_size(ctx):
     """The 1.57M-tet lattice onto 128^3: the two FP64 algorithms on the GPU
-    agree cell by cell (relative to the largest cell), and both totals match
-    the exact sum of the simplex masses."""
+    each match the oracle on every cell to the per-cell bar, and both totals
+    match the exact sum of the simplex masses."""
     prob = synth.zeldovich_3d(n=64, grid=128, sigma_cells=1.5, seed=2)
     x, s, r = _dev(prob)
     gc, tc = ctx.project_corners(x, s, r, [128] * 3, out_mass=True)
     assert ctx.sync_status() == simproj.SP_OK, simproj.sp_last_error()
     gp, tp = ctx.project(x, s, r, [128] * 3, precision="fp64", out_mass=True)
     assert ctx.sync_status() == simproj.SP_OK, simproj.sp_last_error()
-    diff = float((gc - gp).abs().max() / gp.abs().max())
-    print("corner vs clip max diff", diff, flush=True)
-    assert diff <= TOL_CELL
+    ref = oracle.project(prob)
+    # Each cell of this mesh takes the signed terms of many overlapping
+    # simplices (heavy shell crossing): their rounding adds up, so the corner
+    # sums are held to 1e-11 of the coverage scale here (1e-14 on the small
+    # meshes above), the clipping path to its own 1e-12
+    for name, g, tol in (("corners", gc, 1e-11), ("clipping", gp, 1e-12)):
+        err = oracle.cell_error(g.cpu().numpy(), ref)
+        print(name, err, flush=True)
+        assert err["e_cell"] <= tol and err["e_mass"] <= TOL_MASS, (name, err)
     exact = oracle.simplex_mass(prob).sum()
     assert abs(float(tc.cpu()[0]) - exact) <= TOL_MASS * exact
     assert abs(float(tp.cpu()[0]) - exact) <= 1e-12 * exact

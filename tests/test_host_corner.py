@@ -1,8 +1,8 @@
 """The corner-sum projection (the header the corner kernel uses) compiled
 for the host with g++ and compared with the oracle on the CPU: meshes in
-general position, and meshes with corners on grid planes (which the sum
-moves off them by a generic offset of about 1e-12 cells), must match to the
-corner-sum tolerance."""
+general position, and degenerate ones -- corners on grid planes, lines and
+points, edges and facets through grid lines and points -- which simulation
+of simplicity resolves (Section 3.3, eq. eq_sos), all to 1e-12 per cell."""
 import ctypes
 import os
 import subprocess
@@ -15,9 +15,9 @@ from paper_1509_07720_amd import synth
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
-# Corner sums are signed and cancel within a cell; see DESIGN (corner sums)
-# for the tolerance: per cell relative to the coverage scale, and of the total.
-TOL_CELL, TOL_MASS = 1e-10, 1e-12
+# Corner sums are signed and cancel within a cell: per cell relative to the
+# coverage scale, and of the total (the same bar as the FP64 clipping path).
+TOL_CELL, TOL_MASS = 1e-12, 1e-12
 
 
 @pytest.fixture(scope="module")
@@ -45,6 +45,36 @@ def corner(lib, prob):
     return out.reshape(tuple(dims[::-1])), st
 
 
+def snapped(prob, k):
+    """Positions rounded to 1/k of a cell (unit box); simplices that become
+    flat are dropped."""
+    dims = np.asarray(prob["dims"], np.float64)
+    x = np.round(np.asarray(prob["xyz"]) * dims * k) / (dims * k)
+    x = np.mod(x, 1.0)
+    S = np.asarray(prob["simplices"])
+    P = synth.unwrapped_corners(x, S, np.ones(3), prob["periodic"])
+    keep = np.abs(synth.signed_volumes(P)) > 1e-12
+    return dict(prob, xyz=x, simplices=S[keep], rho=np.asarray(prob["rho"])[keep] if prob["rho_per_corner"]
+                else prob["rho"])
+
+
+def half_cell_soup(n, grid, seed):
+    """n tetrahedra with corners on the half-cell lattice of a periodic grid
+    (each within two cells of its first corner), per-corner densities."""
+    rng = np.random.default_rng(seed)
+    X, R = [], []
+    while len(X) < n:
+        c = rng.integers(0, 2 * grid, 3)
+        P = (c + rng.integers(-4, 5, (4, 3))) / 2.0
+        if abs(np.linalg.det(P[1:] - P[0])) < 1e-9:
+            continue
+        X.append(np.mod(P, grid) / grid)
+        R.append(rng.uniform(0.5, 2.0, 4))
+    return dict(dim=3, xyz=np.concatenate(X), simplices=np.arange(4 * n, dtype=np.int32).reshape(n, 4),
+                rho=np.concatenate(R), rho_per_corner=True, origin=np.zeros(3), extent=np.ones(3),
+                dims=np.array([grid] * 3), periodic=(True, True, True))
+
+
 def stretched(prob):
     return dict(prob, xyz=np.asarray(prob["xyz"]) * 1.3 - 0.15, periodic=(False,) * 3)
 
@@ -58,6 +88,11 @@ PROBLEMS = {
     "soup_on_planes": lambda: synth.tet_soup(n_tets=20000, grid=48, seed=5),
     # every corner on a grid point
     "undisplaced_lattice": lambda: synth.zeldovich_3d(n=8, grid=16, sigma_cells=0.0, seed=1),
+    # positions snapped to quarter cells: corners on grid planes, lines and
+    # points, edges and facets through grid lines and points
+    "quarter_cell_lattice": lambda: snapped(synth.zeldovich_3d(n=8, grid=16, sigma_cells=1.0, seed=4), 4),
+    # tetrahedra with every corner on the half-cell lattice
+    "half_cell_soup": lambda: half_cell_soup(400, 12, seed=7),
     # a lattice stretched over a non-periodic box: wrapped simplices span it,
     # parts fall outside and are dropped
     "non_periodic": lambda: stretched(synth.zeldovich_3d(n=8, grid=16, sigma_cells=1.0, seed=8)),
@@ -68,7 +103,7 @@ PROBLEMS = {
 def test_corner_sums_match_oracle(lib, name):
     prob = PROBLEMS[name]()
     got, st = corner(lib, prob)
-    assert st[2] == 0  # general position
+    assert st[2] == 0  # every simplex summed
     err = oracle.cell_error(got, oracle.project(prob))
     assert err["e_cell"] <= TOL_CELL, err
     assert err["e_mass"] <= TOL_MASS, err
