@@ -49,7 +49,7 @@ constexpr int NCLS = 16;     // cost classes
 // Precision route of FP32C problems: a simplex whose bounding box spans
 // WIDE_SPAN cells or more along some axis is clipped and integrated in FP64
 // (its pieces deposited compensated into the FP32 grids).  Positions local
-// to a simplex carry a rounding of half an ulp of its span (R12's u * span),
+// to a simplex carry a rounding of half an ulp of its span (u times the span),
 // and at 64 cells that is 3.8e-6 of a cell, the most the per-cell bound of
 // 1e-5 leaves room for.  Such simplices get the class CLS_WIDE, which no
 // other simplex uses; their work items come first in the list.
@@ -67,6 +67,10 @@ constexpr int maxv3() { return sizeof(T) == 4 ? 14 : 15; }
 constexpr int MAXV3_BIG = 32;
 constexpr int MAXP2 = 12;    // polygon vertices per lane and buffer (peak 8)
 constexpr int OVF_CAP = 1 << 20;  // overflow records per launch (24 MB of scratch)
+// Lanes of a wave that build their next columns together (see k_clip):
+// on the 10M-tet soup 40 measured best among 16..48 and among thresholds
+// relative to the busy lanes (the clip 10 % faster than building at once).
+constexpr int BUILD_MIN = 40;
 
 // Per-call device state, cleared at the start of every call.
 struct CallState {
@@ -792,6 +796,15 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(clip_waves_p
             continue;
         }
         if (!busy) continue;
+        if constexpr (D == 3) {
+            // A column build (a tetrahedron and up to four cuts) costs the
+            // wave the same whether one lane or all of them need it, so a
+            // lane whose column is done waits while other lanes still have
+            // pieces, until BUILD_MIN lanes build together.
+            const bool nb = S.needs_build();
+            const uint64_t bn = __ballot(nb), br = __ballot(!nb);
+            if (nb && br != 0ull && __popcll(bn) < BUILD_MIN) continue;
+        }
         int r;
         if constexpr (D == 3) {
             r = S.step(P3, L, dep);

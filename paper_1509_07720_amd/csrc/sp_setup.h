@@ -250,9 +250,14 @@ SP_HD inline int setup_f32(const float *xyz, int64_t n_vert, const int32_t *simp
 // same cell coordinates as a plain double-precision evaluation.  The inputs
 // may be float (simplices of an FP32C problem clipped in double), upcast
 // exactly.
+//
+// swapped (optional): set when corners 1 and 2 were exchanged to orient the
+// simplex positively (L's corner a is then the input's corner 3 - a for a in
+// {1, 2}).
 template <int D, typename TI = double>
 SP_HD inline int setup_f64(const TI *xyz, int64_t n_vert, const int32_t *simp, int64_t s, const TI *rho,
-                           bool per_corner, const GridDev &g, bool validate, Local<double> &L)
+                           bool per_corner, const GridDev &g, bool validate, Local<double> &L,
+                           bool *swapped = nullptr)
 {
     constexpr int K = D + 1;
     double x[4][3];
@@ -307,6 +312,7 @@ SP_HD inline int setup_f64(const TI *xyz, int64_t n_vert, const int32_t *simp, i
         det = (L.v[1].x - L.v[0].x) * (L.v[2].y - L.v[0].y) - (L.v[1].y - L.v[0].y) * (L.v[2].x - L.v[0].x);
     }
     if (det == 0.0) return SETUP_ZERO_VOLUME;
+    if (swapped) *swapped = det < 0.0;
     if (det < 0.0) {
         V4<double> t = L.v[1];
         L.v[1] = L.v[2];
@@ -477,6 +483,10 @@ struct Sweep3 {
         fail[1] = ry;
         fail[2] = 0;
     }
+
+    // The next step starts by building a column (the current one is done and
+    // slabs remain).
+    SP_HD bool needs_build() const { return iz > zhi && ix < send; }
 
     // One step.  Returns 1 when a piece was processed and more may follow,
     // 0 when the sweep is finished, -1 on a capacity failure.
