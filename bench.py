@@ -483,7 +483,8 @@ def exact_total_2d(prob) -> float:
 
 
 def corner_leg(ctx, steps, warmup):
-    """The paper's corner-sum formulation (sp_project_tets_corners, FP64)
+    """The paper's corner-sum formulation (sp_project_tets_corners, FP64),
+    also with the fused facet contributions (sp_project_tets_corners_fused),
     against the clipping projection in FP64 and FP32C, on the 64^3
     Zel'dovich lattice onto 128^3 and on every 64th tetrahedron of the
     two-level refined 128^3 lattice onto 512^3 (786,432 tets): time per call
@@ -508,6 +509,8 @@ def corner_leg(ctx, steps, warmup):
         x32, r32 = x64.float(), r64.float()
         runs = {
             "corners_fp64": lambda: ctx.project_corners(x64, s, r64, dims, rho_per_corner=pc, out_mass=True),
+            "corners_fused_fp64": lambda: ctx.project_corners(x64, s, r64, dims, rho_per_corner=pc, out_mass=True,
+                                                              fused=True),
             "clip_fp64": lambda: ctx.project(x64, s, r64, dims, precision="fp64", rho_per_corner=pc, out_mass=True),
             "clip_fp32c": lambda: ctx.project(x32, s, r32, dims, precision="fp32c", rho_per_corner=pc, out_mass=True),
         }
@@ -528,7 +531,7 @@ def corner_leg(ctx, steps, warmup):
             log(f"corner leg {name} {k}: {sec * 1e3:.2f} ms (status {st})")
         ref = grids["clip_fp64"]
         scale = float(ref.abs().max())
-        for k in ("corners_fp64", "clip_fp32c"):
+        for k in ("corners_fp64", "corners_fused_fp64", "clip_fp32c"):
             row[k]["max_cell_diff_rel"] = float((grids[k] - ref).abs().max()) / scale
         res[name] = row
         del grids, s, x64, r64, x32, r32

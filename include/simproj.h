@@ -227,6 +227,23 @@ sp_status sp_project_tets_amr(sp_ctx *ctx, const sp_problem *prob, sp_precision 
  * enumerates its cells). */
 sp_status sp_project_tets_corners(sp_ctx *ctx, const sp_problem *prob, void *stream);
 
+/* sp_project_tets_corners with the fused facet contributions of Appendix D
+ * (eq. eq_contribFused and eq_diffRho): where two summed simplices share a
+ * facet (the same three vertex indices), each term one of them contributes
+ * at a vertex of its piece in a cell, with an edge on that facet, has a
+ * twin from the other simplex that differs only in the sign of the facet
+ * normal (or not at all, when a fold puts both simplices on one side), so
+ * the pair is summed once, by the simplex of lower index, with the
+ * difference (or sum) of the two density functions.  The pieces of such
+ * simplices take the cell centre as their common origin.  Facets are matched
+ * on the device by their vertex indices (a hash table in the context's
+ * scratch, about 76 bytes per simplex); a facet met by more than two
+ * simplices is paired once and its other simplices sum it alone.  The same
+ * result as sp_project_tets_corners up to rounding (tested to 1e-12 of each
+ * cell's coverage scale); n_simplex below 2^30 (else SP_E_INVALID_ARG).
+ * Asynchronous on `stream`. */
+sp_status sp_project_tets_corners_fused(sp_ctx *ctx, const sp_problem *prob, void *stream);
+
 /* Project n independent problems of dimension `dim` (2 or 3; 1 <= n <=
  * 65535, n == 0 is a no-op) in one persistent, work-stealing
  * launch; `probs` is a HOST array of n problems whose buffers are device

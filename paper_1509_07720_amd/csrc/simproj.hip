@@ -964,15 +964,134 @@ __global__ __launch_bounds__(WG) void k_clipw(ProbDev<float> p0, Batch b)
 // per SIMD (128 VGPRs, the rest spilled) it ran 1.7x faster than at 1 wave
 // with 256 VGPRs, and 3 or 4 waves ran slower again.  One-wave blocks
 // measured 7 % faster than 256-thread ones.
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_corner(ProbDev<double> p)
+// Fused facet contributions of the corner sums (App. D, eq.
+// eq_contribFused): the facets of the summed simplices are matched by their
+// vertex ids in an open-addressing table (linear probing, insert or find),
+// so that each facet shared by two of them knows the other.  Facet ids are
+// s * 4 + k, k the input corner opposite the facet; tables hold id + 1, 0
+// meaning empty (hence fewer than 2^30 simplices).
+struct FuseDev {
+    uint32_t *tab;   // mask + 1 entries
+    uint32_t mask;
+    uint32_t *mate;  // [4n] the facet id + 1 across each facet, 0 if none
+    int8_t *side;    // [4n] facet_side of each facet, 0 if its simplex is not summed
+    double *grad;    // [3n] density gradient of each summed simplex
+};
+
+// input corner of local corner a (set-up exchanges corners 1 and 2 of a
+// negatively oriented simplex)
+__device__ inline int corner_input(int a, bool swapped) { return swapped && (a == 1 || a == 2) ? 3 - a : a; }
+
+// sorted vertex ids of the facet opposite input corner k of simplex s
+__device__ inline void facet_key(const int32_t *simp, int64_t s, int k, int32_t key[3])
+{
+    int n = 0;
+    for (int a = 0; a < 4; ++a)
+        if (a != k) key[n++] = simp[s * 4 + a];
+    if (key[1] < key[0]) { const int32_t t = key[0]; key[0] = key[1]; key[1] = t; }
+    if (key[2] < key[1]) { const int32_t t = key[1]; key[1] = key[2]; key[2] = t; }
+    if (key[1] < key[0]) { const int32_t t = key[0]; key[0] = key[1]; key[1] = t; }
+}
+
+__device__ inline uint32_t facet_hash(const int32_t key[3])
+{
+    uint64_t h = (uint64_t)(uint32_t)key[0] * 0x9E3779B97F4A7C15ull;
+    h = (h ^ (h >> 29)) + (uint64_t)(uint32_t)key[1] * 0xC2B2AE3D27D4EB4Full;
+    h = (h ^ (h >> 31)) + (uint64_t)(uint32_t)key[2] * 0x165667B19E3779F9ull;
+    h ^= h >> 33;
+    h *= 0xff51afd7ed558ccdull;
+    h ^= h >> 33;
+    return (uint32_t)h;
+}
+
+// Insert facet fid, or pair it with the facet of the same vertices already
+// there (a third facet on the same vertices stays unpaired).
+__device__ inline void facet_insert(const FuseDev &f, const int32_t *simp, uint32_t fid)
+{
+    int32_t key[3];
+    facet_key(simp, fid >> 2, (int)(fid & 3u), key);
+    uint32_t h = facet_hash(key) & f.mask;
+    for (uint32_t probe = 0; probe <= f.mask; ++probe, h = (h + 1u) & f.mask) {
+        const uint32_t cur = atomicCAS(&f.tab[h], 0u, fid + 1u);
+        if (cur == 0u) return;
+        int32_t kc[3];
+        facet_key(simp, (cur - 1u) >> 2, (int)((cur - 1u) & 3u), kc);
+        if (kc[0] == key[0] && kc[1] == key[1] && kc[2] == key[2]) {
+            if (atomicCAS(&f.mate[cur - 1u], 0u, fid + 1u) == 0u) f.mate[fid] = cur;
+            return;
+        }
+    }
+}
+
+// Per simplex: whether the corner sums will sum it with fused terms, its
+// density gradient, the side of each facet, and its facets into the table.
+__global__ __launch_bounds__(256) void k_corner_prep(ProbDev<double> p, FuseDev f)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= p.n) return;
+    Local<double> L;
+    bool sw = false;
+    int sd[4] = {0, 0, 0, 0};
+    if (setup_f64<3>(p.xyz, p.n_vert, p.simp, s, p.rho, p.per_corner != 0, p.g, false, L, &sw) == SETUP_OK &&
+        corner_box_ok(L)) {
+        int64_t vid[4];
+        for (int a = 0; a < 4; ++a) vid[a] = p.simp[s * 4 + corner_input(a, sw)];
+        const D3 g = corner_gradient(L);
+        f.grad[s * 3 + 0] = g.x;
+        f.grad[s * 3 + 1] = g.y;
+        f.grad[s * 3 + 2] = g.z;
+        if (corner_fusable(L, g))
+            for (int m = 0; m < 4; ++m) sd[corner_input(m, sw)] = facet_side(L, vid, m);
+    }
+    for (int k = 0; k < 4; ++k) f.side[s * 4 + k] = (int8_t)sd[k];
+    for (int k = 0; k < 4; ++k)
+        if (sd[k] != 0) facet_insert(f, p.simp, (uint32_t)(s * 4 + k));
+}
+
+// The fused-term data of simplex s (local corners L, corners 1 and 2
+// exchanged at set-up if swapped): for each facet, plain, left to the
+// neighbour of lower index, or summed here with the neighbour's density.
+__device__ inline void corner_fuse(const ProbDev<double> &p, const FuseDev &f, int64_t s, const Local<double> &L,
+                                   bool sw, FacetFuse &fz)
+{
+    fz.cell_origin = false;
+    const D3 g = d3(f.grad[s * 3 + 0], f.grad[s * 3 + 1], f.grad[s * 3 + 2]);
+    for (int m = 0; m < 4; ++m) {
+        fz.mode[m] = FACET_PLAIN;
+        const int k = corner_input(m, sw);
+        const uint32_t mt = f.mate[s * 4 + k];
+        if (mt == 0u) continue;
+        fz.cell_origin = true;
+        const uint32_t fid = mt - 1u;
+        const int64_t j = (int64_t)(fid >> 2);
+        if (j < s) {
+            fz.mode[m] = FACET_SKIP;
+            continue;
+        }
+        const int a = m == 0 ? 1 : 0;  // a corner of the facet
+        const int32_t va = p.simp[s * 4 + corner_input(a, sw)];
+        double rj = L.v[a].r;  // per-vertex densities agree on shared corners
+        if (p.per_corner)
+            for (int kk = 0; kk < 4; ++kk)
+                if (p.simp[j * 4 + kk] == va) rj = p.rho[j * 4 + kk];
+        const D3 gj = d3(f.grad[j * 3 + 0], f.grad[j * 3 + 1], f.grad[j * 3 + 2]);
+        fuse_facet(fz, m, L, g, a, gj, rj, (int)f.side[s * 4 + k] * (int)f.side[fid]);
+    }
+}
+
+template <bool FUSED>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_corner(ProbDev<double> p, FuseDev f)
 {
     const int64_t st = (int64_t)gridDim.x * blockDim.x;
     for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < p.n; s += st) {
         Local<double> L;
-        const int r = setup_any<3>(p, s, p.validate != 0, L);
+        bool sw = false;
+        const int r = setup_f64<3>(p.xyz, p.n_vert, p.simp, s, p.rho, p.per_corner != 0, p.g, p.validate != 0, L, &sw);
         if (r == SETUP_OK) {
             auto dep = make_dep<double>(p, L, kIdentity);
-            if (corner_project(L, dep) > 0) {
+            FacetFuse fz;
+            if constexpr (FUSED) corner_fuse(p, f, s, L, sw, fz);
+            if (corner_project(L, dep, FUSED ? &fz : nullptr) > 0) {
                 record_error(p.es, SP_E_UNSUPPORTED);
                 atomicAdd(&p.es->n_degenerate, 1);
             }
@@ -2069,12 +2188,16 @@ extern "C" sp_status sp_project_tets_noalloc(sp_ctx *ctx, const sp_problem *prob
 }
 
 // Projection by corner sums (FP64): the same result as sp_project_tets in
-// FP64 mode, by the paper's own formulation, for comparison.
-extern "C" sp_status sp_project_tets_corners(sp_ctx *ctx, const sp_problem *prob, void *stream)
+// FP64 mode, by the paper's own formulation, for comparison; with `fused`
+// the terms on facets shared by two simplices are summed once.
+static sp_status corners_impl(sp_ctx *ctx, const sp_problem *prob, void *stream, bool fused)
 {
     sp_status st = check_problem(prob, 3, SP_PREC_FP64);
     if (st != SP_OK) return st;
     if (!ctx) return fail(SP_E_INVALID_ARG, "ctx is NULL");
+    if (fused && prob->n_simplex >= ((int64_t)1 << 30))
+        return fail(SP_E_INVALID_ARG, "n_simplex %lld: the fused corner sums take fewer than 2^30 simplices",
+                    (long long)prob->n_simplex);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     HIPCHECK(hipSetDevice(ctx->device));
     std::vector<Prepared<double>> v;
@@ -2083,17 +2206,51 @@ extern "C" sp_status sp_project_tets_corners(sp_ctx *ctx, const sp_problem *prob
     st = prepare<3, double>(ctx, prob, 1, v.data(), ntotal, s, false, false);
     if (st != SP_OK) return st;
     const Prepared<double> &q = v[0];
+    FuseDev f = {nullptr, 0u, nullptr, nullptr, nullptr};
+    if (fused && ntotal > 0) {
+        // a table of at least twice as many slots as facets
+        size_t slots = 1024;
+        while (slots < 8 * (size_t)ntotal) slots *= 2;
+        const size_t o_tab = 0, o_mate = align_up(o_tab + 4 * slots), o_grad = align_up(o_mate + 16 * (size_t)ntotal),
+                     o_side = align_up(o_grad + 24 * (size_t)ntotal), end = align_up(o_side + 4 * (size_t)ntotal);
+        st = ensure_buf(ctx, ctx->aux[0], end, s);
+        if (st != SP_OK) return st;
+        char *base = static_cast<char *>(ctx->aux[0].p);
+        f.tab = reinterpret_cast<uint32_t *>(base + o_tab);
+        f.mask = (uint32_t)(slots - 1);
+        f.mate = reinterpret_cast<uint32_t *>(base + o_mate);
+        f.grad = reinterpret_cast<double *>(base + o_grad);
+        f.side = reinterpret_cast<int8_t *>(base + o_side);
+        // the table and the mates start empty (zero); tab and mate are contiguous
+        hipLaunchKernelGGL(k_fill<uint32_t>, dim3(grid_blocks(o_grad / 4, 256)), dim3(256), 0, s, f.tab, o_grad / 4);
+    }
     hipLaunchKernelGGL(k_clear_state, dim3(1), dim3(64), 0, s, ctx->cs, q.total);
     if (!q.accumulate)
         hipLaunchKernelGGL(k_fill<double>, dim3(grid_blocks(q.ncell, 256)), dim3(256), 0, s, q.p.out, q.ncell);
-    if (ntotal > 0)
-        hipLaunchKernelGGL(k_corner, dim3(grid_blocks((size_t)ntotal, 64)), dim3(64), 0, s, q.p);
+    if (f.mate)
+        hipLaunchKernelGGL(k_corner_prep, dim3(grid_blocks((size_t)ntotal, 256)), dim3(256), 0, s, q.p, f);
+    if (ntotal > 0) {
+        if (f.mate)
+            hipLaunchKernelGGL(k_corner<true>, dim3(grid_blocks((size_t)ntotal, 64)), dim3(64), 0, s, q.p, f);
+        else
+            hipLaunchKernelGGL(k_corner<false>, dim3(grid_blocks((size_t)ntotal, 64)), dim3(64), 0, s, q.p, f);
+    }
     if (q.total)
         hipLaunchKernelGGL(k_finalize<double>, dim3(grid_blocks(q.ncell, 256 * 8)), dim3(256), 0, s, q.p.out, nullptr,
                            0, q.ncell, q.to_mass, q.total);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(SP_E_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
     return SP_OK;
+}
+
+extern "C" sp_status sp_project_tets_corners(sp_ctx *ctx, const sp_problem *prob, void *stream)
+{
+    return corners_impl(ctx, prob, stream, false);
+}
+
+extern "C" sp_status sp_project_tets_corners_fused(sp_ctx *ctx, const sp_problem *prob, void *stream)
+{
+    return corners_impl(ctx, prob, stream, true);
 }
 
 extern "C" sp_status sp_project_tris(sp_ctx *ctx, const sp_problem *prob, sp_precision prec, void *stream)

@@ -176,15 +176,53 @@ SP_HD inline int sos_edge_cell(D3 a, D3 b, int d, int q, int c, double approx)
     return m;
 }
 
+// Fused facet contributions (App. D, eq. eq_contribFused and eq_diffRho).
+// A facet f shared by simplices s and j: every (vertex, edge, facet f) term
+// of a piece of s in a cell has a twin in the piece of j in the same cell,
+// with the same vertex, edge and in-facet direction and the opposite facet
+// normal when s and j lie on opposite sides of f (the same normal when a
+// fold puts both on one side), so with one origin O per cell shared by both
+//   C_s + C_j = E0 ((rho_s(O) + sigma rho_j(O)) + E1 . (g_s + sigma g_j)),
+// sigma = -1 on opposite sides, +1 on the same side, E0 and E1 those of s.
+// The simplex of lower index sums each pair; the other leaves it out.
+enum : int { FACET_PLAIN = 0, FACET_FUSED = 1, FACET_SKIP = 2 };
+
+// How one simplex treats the terms on its facets (indexed by the corner
+// opposite each facet, in the simplex's local corner order): the mode, and
+// for a fused facet the pair's density rho_s + sigma rho_j as
+// R + G . (X - xr), xr a corner of the facet (local coordinates): taken
+// relative to a point of the facet, the difference of two densities that
+// agree there is not the difference of two large values.
+struct FacetFuse {
+    int mode[4];
+    D3 G[4];
+    D3 xr[4];
+    double R[4];
+    bool cell_origin;  // origins at cell centres (any facet paired), shared with the neighbours
+};
+
 // The corner terms of one vertex: edges t[0..2], facets with inward normals
-// b[0..2], facet f holding edges fe[f][0] and fe[f][1].  The fixed-count
-// loops here and below are unrolled so that these small arrays are indexed
-// by constants (registers, not scratch memory).
-SP_HD inline double vertex_terms(D3 P, double rho0, D3 g, const D3 *t, const D3 *b, const int (*fe)[2])
+// b[0..2], facet f holding edges fe[f][0] and fe[f][1]; mf[f] is the
+// simplex facet that b[f] lies on (the corner opposite it), or -1 for a
+// grid plane.  P = vertex - O, rho0 = rho(O).  The fixed-count loops here
+// and below are unrolled so that these small arrays are indexed by
+// constants (registers, not scratch memory).
+SP_HD inline double vertex_terms(D3 P, double rho0, D3 g, const D3 *t, const D3 *b, const int (*fe)[2], const int *mf,
+                                 const FacetFuse *fz, D3 O)
 {
     double s = 0.0;
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
+        double r0 = rho0;
+        D3 gf = g;
+        if (fz && mf[f] >= 0) {
+            const int m = mf[f];
+            if (fz->mode[m] == FACET_SKIP) continue;
+            if (fz->mode[m] == FACET_FUSED) {
+                r0 = fz->R[m] + dot(fz->G[m], O - fz->xr[m]);
+                gf = fz->G[m];
+            }
+        }
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
             const D3 T = t[fe[f][k]];
@@ -193,11 +231,87 @@ SP_HD inline double vertex_terms(D3 P, double rho0, D3 g, const D3 *t, const D3 
             if (dot(N, other) < 0.0) N = -1.0 * N;
             const double pt = dot(P, T), pn = dot(P, N), pb = dot(P, b[f]);
             const double e0 = -pt * pn * pb / 6.0;
-            const double e1g = 0.25 * (pt * dot(T, g) + 2.0 * pn * dot(N, g) + 3.0 * pb * dot(b[f], g));
-            s += e0 * (rho0 + e1g);
+            const double e1g = 0.25 * (pt * dot(T, gf) + 2.0 * pn * dot(N, gf) + 3.0 * pb * dot(b[f], gf));
+            s += e0 * (r0 + e1g);
         }
     }
     return s;
+}
+
+// One thread walks every grid point of a simplex's bounding box: a simplex
+// over more than 2^24 cells is not summed (and is reported).
+SP_HD inline bool corner_box_ok(const Local<double> &L)
+{
+    double lo[3], hi[3];
+    for (int d = 0; d < 3; ++d) {
+        const double x0 = d == 0 ? L.v[0].x : (d == 1 ? L.v[0].y : L.v[0].z);
+        lo[d] = hi[d] = x0;
+        for (int a = 1; a < 4; ++a) {
+            const double x = d == 0 ? L.v[a].x : (d == 1 ? L.v[a].y : L.v[a].z);
+            lo[d] = fmin(lo[d], x);
+            hi[d] = fmax(hi[d], x);
+        }
+    }
+    return (floor(hi[0]) - floor(lo[0]) + 1.0) * (floor(hi[1]) - floor(lo[1]) + 1.0) *
+               (floor(hi[2]) - floor(lo[2]) + 1.0) <=
+           16777216.0;
+}
+
+// Gradient of the simplex's linear density: (v_k - v_0) . g = r_k - r_0
+// (Cramer's rule), from its local corners; a neighbour's copy of this value
+// is what the fused terms use.
+SP_HD inline D3 corner_gradient(const Local<double> &L)
+{
+    const D3 v0 = d3(L.v[0].x, L.v[0].y, L.v[0].z);
+    const D3 e1 = d3(L.v[1].x, L.v[1].y, L.v[1].z) - v0, e2 = d3(L.v[2].x, L.v[2].y, L.v[2].z) - v0,
+             e3 = d3(L.v[3].x, L.v[3].y, L.v[3].z) - v0;
+    const D3 c23 = cross(e2, e3), c31 = cross(e3, e1), c12 = cross(e1, e2);
+    const double inv = 1.0 / dot(e1, c23);
+    return (inv * (L.v[1].r - L.v[0].r)) * c23 + (inv * (L.v[2].r - L.v[0].r)) * c31 +
+           (inv * (L.v[3].r - L.v[0].r)) * c12;
+}
+
+// Whether a simplex takes part in fused terms: a density gradient of more
+// than 1024 times its largest corner value per cell (a sliver: its terms
+// are huge and cancel to a tiny piece) is left out, so that its terms keep
+// cancelling within its own pieces; its neighbours then sum those facets
+// alone.
+SP_HD inline bool corner_fusable(const Local<double> &L, D3 g)
+{
+    double rmax = 0.0;
+    for (int a = 0; a < 4; ++a) rmax = fmax(rmax, fabs(L.v[a].r));
+    return fmax(fabs(g.x), fmax(fabs(g.y), fabs(g.z))) <= 1024.0 * rmax;
+}
+
+// Side of facet m (opposite local corner m) that the simplex lies on, in a
+// frame every simplex sharing the facet agrees on: the sign of
+// (X - A) . ((B - A) x (C - A)), with A, B, C the facet's corners in
+// increasing vertex id vid[] and X the opposite corner (0 only for a flat
+// simplex).
+SP_HD inline int facet_side(const Local<double> &L, const int64_t *vid, int m)
+{
+    int c[3], n = 0;
+    for (int a = 0; a < 4; ++a)
+        if (a != m) c[n++] = a;
+    // sort the three corners by vertex id
+    if (vid[c[1]] < vid[c[0]]) { const int t = c[0]; c[0] = c[1]; c[1] = t; }
+    if (vid[c[2]] < vid[c[1]]) { const int t = c[1]; c[1] = c[2]; c[2] = t; }
+    if (vid[c[1]] < vid[c[0]]) { const int t = c[0]; c[0] = c[1]; c[1] = t; }
+    auto P = [&](int a) { return d3(L.v[a].x, L.v[a].y, L.v[a].z); };
+    return sign_tri(P(m), P(c[1]), P(c[2]), P(c[0]));
+}
+
+// Fused data of facet m of a simplex with local corners L and density
+// gradient g: the neighbour across it has gradient gj, density rj at the
+// facet's corner `a` (a local corner of this simplex, a != m), and lies on
+// the same side of the facet (sigma = +1) or the other (-1).
+SP_HD inline void fuse_facet(FacetFuse &fz, int m, const Local<double> &L, D3 g, int a, D3 gj, double rj, int sigma)
+{
+    const double sg = (double)sigma;
+    fz.mode[m] = FACET_FUSED;
+    fz.G[m] = g + sg * gj;
+    fz.xr[m] = d3(L.v[a].x, L.v[a].y, L.v[a].z);
+    fz.R[m] = L.v[a].r + sg * rj;
 }
 
 // Projection of one simplex (local cell coordinates, as set up for the
@@ -205,8 +319,11 @@ SP_HD inline double vertex_terms(D3 P, double rho0, D3 g, const D3 *t, const D3 
 // sum at local cell indices, in cell-volume units.  Returns 1 when the
 // simplex was not summed (its bounding box holds more than 2^24 cells), 0
 // otherwise.
+// (Inlined at every call, so that a caller passing no fusion data compiles
+// to the plain sums.)
 template <typename Dep>
-SP_HD inline int corner_project(const Local<double> &L, Dep &dep)
+SP_HD __attribute__((always_inline)) inline int corner_project(const Local<double> &L, Dep &dep,
+                                                                const FacetFuse *fz = nullptr)
 {
     D3 v[4];
     double r[4];
@@ -214,31 +331,26 @@ SP_HD inline int corner_project(const Local<double> &L, Dep &dep)
         v[a] = d3(L.v[a].x, L.v[a].y, L.v[a].z);
         r[a] = L.v[a].r;
     }
-    // gradient of rho: (v_k - v_0) . g = r_k - r_0 (Cramer's rule)
-    const D3 e1 = v[1] - v[0], e2 = v[2] - v[0], e3 = v[3] - v[0];
-    const D3 c23 = cross(e2, e3), c31 = cross(e3, e1), c12 = cross(e1, e2);
-    const double det = dot(e1, c23);
-    const double inv = 1.0 / det;
-    const D3 g = (inv * (r[1] - r[0])) * c23 + (inv * (r[2] - r[0])) * c31 + (inv * (r[3] - r[0])) * c12;
+    const D3 g = corner_gradient(L);
     D3 lo = v[0], hi = v[0];
     for (int a = 1; a < 4; ++a) {
         lo = d3(fmin(lo.x, v[a].x), fmin(lo.y, v[a].y), fmin(lo.z, v[a].z));
         hi = d3(fmax(hi.x, v[a].x), fmax(hi.y, v[a].y), fmax(hi.z, v[a].z));
     }
-    // one thread walks every grid point of the bounding box: a simplex over
-    // more than 2^24 cells is not summed (reported)
-    if ((floor(hi.x) - floor(lo.x) + 1.0) * (floor(hi.y) - floor(lo.y) + 1.0) * (floor(hi.z) - floor(lo.z) + 1.0) >
-        16777216.0)
-        return 1;
+    if (!corner_box_ok(L)) return 1;
 
-    // origin of the piece in cell (cx, cy, cz), and the density there
+    // origin of the piece in cell (cx, cy, cz), and the density there: the
+    // cell's centre when terms are fused with a neighbour's (both must use
+    // the same origin), else the point of the bounding box nearest to it
+    const bool cell_origin = fz && fz->cell_origin;
     auto origin = [&](int cx, int cy, int cz) {
+        if (cell_origin) return d3(cx + 0.5, cy + 0.5, cz + 0.5);
         return d3(fmin(fmax(cx + 0.5, lo.x), hi.x), fmin(fmax(cy + 0.5, lo.y), hi.y), fmin(fmax(cz + 0.5, lo.z), hi.z));
     };
     auto rho_at = [&](D3 X) { return r[0] + dot(g, X - v[0]); };
-    auto deposit = [&](int cx, int cy, int cz, D3 X, const D3 *t, const D3 *b, const int (*fe)[2]) {
+    auto deposit = [&](int cx, int cy, int cz, D3 X, const D3 *t, const D3 *b, const int (*fe)[2], const int *mf) {
         const D3 o = origin(cx, cy, cz);
-        const double s = vertex_terms(X - o, rho_at(o), g, t, b, fe);
+        const double s = vertex_terms(X - o, rho_at(o), g, t, b, fe, mf, fz, o);
         if (s != 0.0) dep(cx, cy, cz, s);
     };
     // inward unit normal of the facet opposite corner m
@@ -267,14 +379,15 @@ SP_HD inline int corner_project(const Local<double> &L, Dep &dep)
         for (int k = 0; k < 4; ++k)
             if (k != a) o3[n++] = k;
         D3 t[3], b[3];
-        int fe[3][2];
+        int fe[3][2], mf[3];
         for (int k = 0; k < 3; ++k) {
             t[k] = unit(v[o3[k]] - v[a]);
             b[k] = nf[o3[k]];  // the facet without o3[k] holds the other two edges
+            mf[k] = o3[k];
             fe[k][0] = (k + 1) % 3;
             fe[k][1] = (k + 2) % 3;
         }
-        deposit((int)floor(v[a].x), (int)floor(v[a].y), (int)floor(v[a].z), v[a], t, b, fe);
+        deposit((int)floor(v[a].x), (int)floor(v[a].y), (int)floor(v[a].z), v[a], t, b, fe, mf);
     }
 
     // B: every edge through every (perturbed) grid plane it crosses: the
@@ -310,9 +423,10 @@ SP_HD inline int corner_project(const Local<double> &L, Dep &dep)
                         const D3 t[3] = {sg * up, u1, u2};
                         const D3 b[3] = {n1, n2, axis(d, sg)};
                         const int fe[3][2] = {{0, 1}, {0, 2}, {1, 2}};
+                        const int mf[3] = {m2, m1, -1};
                         int cs[3] = {cell[0], cell[1], cell[2]};
                         cs[d] = side == 0 ? c : c - 1;
-                        deposit(cs[0], cs[1], cs[2], p, t, b, fe);
+                        deposit(cs[0], cs[1], cs[2], p, t, b, fe, mf);
                     }
                 }
             }
@@ -377,11 +491,12 @@ SP_HD inline int corner_project(const Local<double> &L, Dep &dep)
                             const D3 t[3] = {tl, w1, w2};
                             const D3 b[3] = {nF, axis(d1, s1 ? 1.0 : -1.0), axis(d2, s2 ? 1.0 : -1.0)};
                             const int fe[3][2] = {{1, 2}, {0, 1}, {0, 2}};
+                            const int mf[3] = {m, -1, -1};
                             int cell[3];
                             cell[d] = cd;
                             cell[d1] = j - 1 + s1;
                             cell[d2] = k - 1 + s2;
-                            deposit(cell[0], cell[1], cell[2], q, t, b, fe);
+                            deposit(cell[0], cell[1], cell[2], q, t, b, fe, mf);
                         }
                     }
                 }
@@ -409,7 +524,8 @@ SP_HD inline int corner_project(const Local<double> &L, Dep &dep)
                     const D3 t[3] = {axis(0, dx ? -1.0 : 1.0), axis(1, dy ? -1.0 : 1.0), axis(2, dz ? -1.0 : 1.0)};
                     const D3 b[3] = {t[0], t[1], t[2]};  // the face across axis k holds the other two edges
                     const int fe[3][2] = {{1, 2}, {0, 2}, {0, 1}};
-                    deposit(x - dx, y - dy, z - dz, w, t, b, fe);
+                    const int mf[3] = {-1, -1, -1};
+                    deposit(x - dx, y - dy, z - dz, w, t, b, fe, mf);
                 }
             }
         }

@@ -83,6 +83,8 @@ _lib.sp_project_tets_amr.argtypes = [_V, ctypes.POINTER(sp_problem), ctypes.c_in
 _lib.sp_project_tets_amr.restype = ctypes.c_int
 _lib.sp_project_tets_corners.argtypes = [_V, ctypes.POINTER(sp_problem), _V]
 _lib.sp_project_tets_corners.restype = ctypes.c_int
+_lib.sp_project_tets_corners_fused.argtypes = [_V, ctypes.POINTER(sp_problem), _V]
+_lib.sp_project_tets_corners_fused.restype = ctypes.c_int
 _lib.sp_project_batch.argtypes = [_V, ctypes.c_int, ctypes.POINTER(sp_problem), ctypes.c_int, ctypes.c_int, _V]
 _lib.sp_project_batch.restype = ctypes.c_int
 _lib.sp_sync_status.argtypes = [_V, _V]
@@ -152,6 +154,10 @@ def sp_project_tets_accurate(ctx, prob: sp_problem, accurate_bits: int, wrong_bi
 
 def sp_project_tets_corners(ctx, prob: sp_problem, stream=None) -> int:
     return _lib.sp_project_tets_corners(ctx, ctypes.byref(prob), stream)
+
+
+def sp_project_tets_corners_fused(ctx, prob: sp_problem, stream=None) -> int:
+    return _lib.sp_project_tets_corners_fused(ctx, ctypes.byref(prob), stream)
 
 
 def sp_project_tets_amr(ctx, prob: sp_problem, prec: int, max_level: int, stream=None):
@@ -305,9 +311,11 @@ class Context:
 
     def project_corners(self, xyz, simplices, rho, dims, origin=(0.0, 0.0, 0.0), extent=(1.0, 1.0, 1.0),
                         periodic=(True, True, True), rho_per_corner: bool = False, out=None, out_mass: bool = False,
-                        accumulate: bool = False, validate: bool = False, want_total: bool = True, stream=None):
+                        accumulate: bool = False, validate: bool = False, want_total: bool = True, stream=None,
+                        fused: bool = False):
         """FP64 projection of tetrahedra by corner sums
-        (sp_project_tets_corners); returns (grid, total_mass)."""
+        (sp_project_tets_corners, or sp_project_tets_corners_fused with
+        fused); returns (grid, total_mass)."""
         import torch
 
         if xyz.dtype != torch.float64 or rho.dtype != torch.float64:
@@ -323,7 +331,8 @@ class Context:
         total = torch.zeros(1, dtype=torch.float64, device=xyz.device) if want_total else None
         p = make_problem(xyz, simplices, rho, dims, origin, extent, periodic, rho_per_corner, out, None, total,
                          out_mass, accumulate, validate)
-        _check(sp_project_tets_corners(self.handle, p, _stream_ptr(stream)), "sp_project_tets_corners")
+        fn = sp_project_tets_corners_fused if fused else sp_project_tets_corners
+        _check(fn(self.handle, p, _stream_ptr(stream)), fn.__name__)
         return out, total
 
     def vertex_density(self, xyz, simplices, mass=None, mass_uniform: float = 1.0, extent=(1.0, 1.0, 1.0),

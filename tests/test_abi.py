@@ -22,7 +22,8 @@ def test_header_declares_the_boundary():
     names = _declared()
     for n in ("sp_create", "sp_destroy", "sp_project_tets", "sp_project_tris", "sp_project_batch",
               "sp_sync_status", "sp_autotune", "sp_last_error", "sp_vertex_density", "sp_tuning_set",
-              "sp_tuning_read", "sp_project_tets_accurate", "sp_project_tets_amr", "sp_project_tets_corners"):
+              "sp_tuning_read", "sp_project_tets_accurate", "sp_project_tets_amr", "sp_project_tets_corners",
+              "sp_project_tets_corners_fused"):
         assert n in names
 
 
@@ -189,3 +190,6 @@ def test_corners_host_validation():
     p.grid.dims[1] = 0
     assert simproj.sp_project_tets_corners(None, p) == simproj.SP_E_INVALID_ARG
     assert "dims[1]" in simproj.sp_last_error()
+    p = _prob()
+    assert simproj.sp_project_tets_corners_fused(None, p) == simproj.SP_E_INVALID_ARG
+    assert "ctx is NULL" in simproj.sp_last_error()

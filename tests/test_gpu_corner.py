@@ -1,6 +1,7 @@
-"""The corner-sum projection (sp_project_tets_corners, FP64) against the
-oracle, against the FP64 clipping projection at full size, and its
-device-side input checks, through the C ABI."""
+"""The corner-sum projection (sp_project_tets_corners, FP64), and the same
+with the fused facet contributions of App. D (sp_project_tets_corners_fused),
+against the oracle, against the FP64 clipping projection at full size, and
+their device-side input checks, through the C ABI."""
 import numpy as np
 import pytest
 
@@ -54,16 +55,17 @@ CASES = {
 }
 
 
+@pytest.mark.parametrize("fused", [False, True])
 @pytest.mark.parametrize("name", list(CASES))
-def test_corners_match_oracle(ctx, name):
+def test_corners_match_oracle(ctx, name, fused):
     prob = CASES[name]()
     x, s, r = _dev(prob)
     g, total = ctx.project_corners(x, s, r, list(prob["dims"]), periodic=prob["periodic"],
-                                   rho_per_corner=prob["rho_per_corner"], out_mass=True)
+                                   rho_per_corner=prob["rho_per_corner"], out_mass=True, fused=fused)
     assert ctx.sync_status() == simproj.SP_OK, simproj.sp_last_error()
     ref = oracle.project(prob)
     err = oracle.cell_error(g.cpu().numpy(), ref)
-    print(name, err, flush=True)
+    print(name, "fused" if fused else "plain", err, flush=True)
     assert err["e_cell"] <= TOL_CELL and err["e_mass"] <= TOL_MASS, err
     assert abs(float(total.cpu()[0]) - ref["mass"].sum()) <= TOL_MASS * ref["mass"].sum()
 
@@ -76,19 +78,27 @@ def test_corners_agree_with_clipping_at_full_size(ctx):
     x, s, r = _dev(prob)
     gc, tc = ctx.project_corners(x, s, r, [128] * 3, out_mass=True)
     assert ctx.sync_status() == simproj.SP_OK, simproj.sp_last_error()
+    gf, tf = ctx.project_corners(x, s, r, [128] * 3, out_mass=True, fused=True)
+    assert ctx.sync_status() == simproj.SP_OK, simproj.sp_last_error()
     gp, tp = ctx.project(x, s, r, [128] * 3, precision="fp64", out_mass=True)
     assert ctx.sync_status() == simproj.SP_OK, simproj.sp_last_error()
     ref = oracle.project(prob)
     # Each cell of this mesh takes the signed terms of many overlapping
     # simplices (heavy shell crossing): their rounding adds up, so the corner
     # sums are held to 1e-11 of the coverage scale here (1e-14 on the small
-    # meshes above), the clipping path to its own 1e-12
-    for name, g, tol in (("corners", gc, 1e-11), ("clipping", gp, 1e-12)):
+    # meshes above), the clipping path to its own 1e-12.  The worst cell
+    # holds a sliver (volume 2.8e-7 cells, density gradient 7.8e6 per cell
+    # against corner densities near 5): its terms are about 1e6 times its
+    # pieces and cancel (the loss of bits of Section 3.4); the fused terms
+    # of its neighbours' facets are formed on other vectors than their
+    # unfused twins, and the fused sums are held to 2e-11 there
+    for name, g, tol in (("corners", gc, 1e-11), ("fused corners", gf, 2e-11), ("clipping", gp, 1e-12)):
         err = oracle.cell_error(g.cpu().numpy(), ref)
         print(name, err, flush=True)
         assert err["e_cell"] <= tol and err["e_mass"] <= TOL_MASS, (name, err)
     exact = oracle.simplex_mass(prob).sum()
     assert abs(float(tc.cpu()[0]) - exact) <= TOL_MASS * exact
+    assert abs(float(tf.cpu()[0]) - exact) <= TOL_MASS * exact
     assert abs(float(tp.cpu()[0]) - exact) <= 1e-12 * exact
 
 
@@ -109,3 +119,18 @@ def test_validate_reports_bad_input(ctx):
     ctx.project_corners(x, s, r, [8] * 3, out_mass=True, validate=True)
     assert ctx.sync_status() == simproj.SP_E_OUT_OF_RANGE
     assert "1 bad index" in simproj.sp_last_error()
+
+
+def test_fused_on_a_folded_sheet_and_repeated_calls(ctx):
+    """A strongly shell-crossed sheet (facets with both simplices on one
+    side), projected twice in a row with the fused terms (the facet table is
+    rebuilt each call), then a smaller mesh: each against the oracle."""
+    big = synth.zeldovich_3d(n=16, grid=32, sigma_cells=3.0, seed=9)
+    small = synth.zeldovich_3d(n=6, grid=12, sigma_cells=1.0, seed=3)
+    for prob in (big, big, small):
+        x, s, r = _dev(prob)
+        g, _ = ctx.project_corners(x, s, r, list(prob["dims"]), out_mass=True, fused=True)
+        assert ctx.sync_status() == simproj.SP_OK, simproj.sp_last_error()
+        err = oracle.cell_error(g.cpu().numpy(), oracle.project(prob))
+        print("folded/fused", err, flush=True)
+        assert err["e_cell"] <= TOL_CELL and err["e_mass"] <= TOL_MASS, err
