@@ -1301,19 +1301,23 @@ __device__ inline bool amr_corners(const ProbDev<T> &p, int64_t s, double P[4][3
 }
 
 // Interiors of the tetrahedron P and the box lo + [0, size]^3 intersect:
-// separating axis test over the 3 axes, the 4 face normals and the 18 edge x
-// axis products, strict on every non-zero axis.  Evaluated without fused
-// multiply-adds, in the order written (the same FP64 steps decide the same
-// way on any implementation that takes them).
-__device__ inline bool amr_meets(const double n[25][3], const double P[4][3], const double lo[3], double size)
+// separating axis test over the 3 axes, the 4 face normals (corners
+// {1,2,3}, {0,2,3}, {0,1,3}, {0,1,2}: (c1 - c0) x (c2 - c0)) and the 18
+// products of the 6 edges (c1 - c0 for {0,1}, {0,2}, {0,3}, {1,2}, {1,3},
+// {2,3}) with the axes, strict on every non-zero axis.  Evaluated without
+// fused multiply-adds, each normal and projection in the order written (the
+// same FP64 steps decide the same way on any implementation that takes
+// them); the normals are formed as they are tested, which keeps the kernel
+// in few registers.
+__device__ inline bool amr_meets(const double P[4][3], const double lo[3], double size)
 {
 #pragma clang fp contract(off)
     double rel[4][3];
     for (int a = 0; a < 4; ++a)
         for (int d = 0; d < 3; ++d) rel[a][d] = P[a][d] - lo[d];
-    for (int k = 0; k < 25; ++k) {
-        const double nx = n[k][0], ny = n[k][1], nz = n[k][2];
-        if (nx == 0.0 && ny == 0.0 && nz == 0.0) continue;
+    // separated along (nx, ny, nz)?
+    auto sep = [&](double nx, double ny, double nz) {
+        if (nx == 0.0 && ny == 0.0 && nz == 0.0) return false;
         double tmin = 0.0, tmax = 0.0;
         for (int a = 0; a < 4; ++a) {
             const double t = (nx * rel[a][0] + ny * rel[a][1]) + nz * rel[a][2];
@@ -1323,37 +1327,63 @@ __device__ inline bool amr_meets(const double n[25][3], const double P[4][3], co
         const double sx = nx * size, sy = ny * size, sz = nz * size;
         const double bmin = (fmin(0.0, sx) + fmin(0.0, sy)) + fmin(0.0, sz);
         const double bmax = (fmax(0.0, sx) + fmax(0.0, sy)) + fmax(0.0, sz);
-        if (!(tmin < bmax && bmin < tmax)) return false;
-    }
-    return true;
-}
-
-__device__ inline void amr_axes(const double P[4][3], double n[25][3])
-{
-#pragma clang fp contract(off)
-    n[0][0] = 1.0, n[0][1] = 0.0, n[0][2] = 0.0;
-    n[1][0] = 0.0, n[1][1] = 1.0, n[1][2] = 0.0;
-    n[2][0] = 0.0, n[2][1] = 0.0, n[2][2] = 1.0;
+        return !(tmin < bmax && bmin < tmax);
+    };
+    if (sep(1.0, 0.0, 0.0) || sep(0.0, 1.0, 0.0) || sep(0.0, 0.0, 1.0)) return false;
     const int F[4][3] = {{1, 2, 3}, {0, 2, 3}, {0, 1, 3}, {0, 1, 2}};
+#pragma unroll 1
     for (int f = 0; f < 4; ++f) {
         double e1[3], e2[3];
         for (int d = 0; d < 3; ++d) {
             e1[d] = P[F[f][1]][d] - P[F[f][0]][d];
             e2[d] = P[F[f][2]][d] - P[F[f][0]][d];
         }
-        n[3 + f][0] = e1[1] * e2[2] - e1[2] * e2[1];
-        n[3 + f][1] = e1[2] * e2[0] - e1[0] * e2[2];
-        n[3 + f][2] = e1[0] * e2[1] - e1[1] * e2[0];
+        if (sep(e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]))
+            return false;
     }
     const int E[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+#pragma unroll 1
     for (int k = 0; k < 6; ++k) {
         double e[3];
         for (int d = 0; d < 3; ++d) e[d] = P[E[k][1]][d] - P[E[k][0]][d];
-        double *a = n[7 + 3 * k];
-        a[0] = 0.0, a[1] = e[2], a[2] = -e[1];
-        a[3] = -e[2], a[4] = 0.0, a[5] = e[0];
-        a[6] = e[1], a[7] = -e[0], a[8] = 0.0;
+        if (sep(0.0, e[2], -e[1]) || sep(-e[2], 0.0, e[0]) || sep(e[1], -e[0], 0.0)) return false;
     }
+    return true;
+}
+
+// A corner of P lies inside the box lo + [0, size]^3 by a margin of
+// size / 2^20 on every axis: no axis then separates them, whatever the
+// rounding of the test above, so the test can be skipped.
+__device__ inline bool amr_corner_inside(const double P[4][3], const double lo[3], double size)
+{
+    const double m = size * 0x1p-20;
+    for (int a = 0; a < 4; ++a) {
+        bool in = true;
+        for (int d = 0; d < 3; ++d) in = in && P[a][d] > lo[d] + m && P[a][d] < lo[d] + size - m;
+        if (in) return true;
+    }
+    return false;
+}
+
+// One slot per lane in counter ctr[key], claimed with one atomic per key
+// present in the wave (the lanes of a key take consecutive slots).  Every
+// active lane of the wave must call it.
+__device__ inline unsigned wave_claim(unsigned *ctr, int key)
+{
+    const int lane = (int)__lane_id();
+    uint64_t todo = __ballot(1);
+    unsigned slot = 0u;
+    while (todo) {
+        const int first = __builtin_ctzll(todo);
+        const int k = __shfl(key, first);
+        const uint64_t m = __ballot(key == k) & todo;
+        unsigned base = 0u;
+        if (lane == first) base = atomicAdd(&ctr[k], (unsigned)__popcll(m));
+        base = __shfl(base, first);
+        if ((m >> lane) & 1ull) slot = base + (unsigned)__popcll(m & ((1ull << lane) - 1ull));
+        todo &= ~m;
+    }
+    return slot;
 }
 
 // Blocks of side 2^l of a grid with dims: their counts per axis and the
@@ -1422,8 +1452,6 @@ __global__ __launch_bounds__(64) void k_amr_mark(ProbDev<T> p, int max_level, co
     if (l > max_level) return;
     double P[4][3];
     if (!amr_corners(p, s, P)) return;
-    double n[25][3];
-    amr_axes(P, n);
     const double size = (double)(1 << l);
     int blo[3], bhi[3];
     for (int d = 0; d < 3; ++d) {
@@ -1453,8 +1481,10 @@ __global__ __launch_bounds__(64) void k_amr_mark(ProbDev<T> p, int max_level, co
                 int wx = bx;
                 if (p.g.periodic[0]) wx = wrap_index(bx, nb[0]);
                 else if (bx < 0 || bx >= nb[0]) continue;
+                uint8_t *mk = m + ((size_t)wz * nb[1] + wy) * nb[0] + wx;
+                if (*mk) continue;  // marked already (by another simplex)
                 const double lo[3] = {bx * size, by * size, bz * size};
-                if (all || amr_meets(n, P, lo, size)) m[((size_t)wz * nb[1] + wy) * nb[0] + wx] = 1;
+                if (all || amr_corner_inside(P, lo, size) || amr_meets(P, lo, size)) *mk = 1;
             }
         }
     }
@@ -1525,17 +1555,21 @@ __global__ __launch_bounds__(64) void k_amr_plevel(ProbDev<T> p, uint8_t *level,
         l = 0;
     }
     level[s] = (uint8_t)l;
-    atomicAdd(&counts[l], 1u);
+    (void)wave_claim(counts, l);
 }
+
+struct AmrBases {
+    unsigned b[16];  // first compacted slot of each level
+};
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_amr_scatter(ProbDev<T> p, const uint8_t *level, unsigned *cursor,
-                                                     const unsigned *base, int32_t *simp, T *rho)
+                                                     AmrBases base, int32_t *simp, T *rho)
 {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= p.n) return;
     const int lv = level[s];
-    const int64_t t = (int64_t)base[lv] + atomicAdd(&cursor[lv], 1u);
+    const int64_t t = (int64_t)base.b[lv] + wave_claim(cursor, lv);
     for (int a = 0; a < 4; ++a) {
         simp[t * 4 + a] = p.simp[s * 4 + a];
         if (rho) rho[t * 4 + a] = p.rho[s * 4 + a];
@@ -2403,7 +2437,7 @@ static sp_status amr_impl(sp_ctx *ctx, const sp_problem *prob, sp_precision prec
             mark_bytes = align_up(mark_bytes + nblk[l]);
         }
     }
-    // buffers: levels, counters, bases, compacted simplices (and corner
+    // buffers: levels, counters, cursors, compacted simplices (and corner
     // densities), marks, one summed grid per level >= 1
     size_t off = 0;
     const size_t o_lv = off;
@@ -2427,7 +2461,6 @@ static sp_status amr_impl(sp_ctx *ctx, const sp_problem *prob, sp_precision prec
     uint8_t *lv = reinterpret_cast<uint8_t *>(base + o_lv);
     unsigned *counts = reinterpret_cast<unsigned *>(base + o_cnt);
     unsigned *cursor = counts + 16;
-    unsigned *bases = counts + 32;
     int32_t *simp = reinterpret_cast<int32_t *>(base + o_simp);
     T *rho = per_corner ? reinterpret_cast<T *>(base + o_rho) : nullptr;
     uint8_t *marks = reinterpret_cast<uint8_t *>(base + o_marks);
@@ -2453,11 +2486,12 @@ static sp_status amr_impl(sp_ctx *ctx, const sp_problem *prob, sp_precision prec
         hipLaunchKernelGGL(k_amr_plevel<T>, dim3(nb64), dim3(64), 0, s, pin, lv, (const uint8_t *)marks, L, counts);
         HIPCHECK(hipMemcpyAsync(hc, counts, sizeof hc, hipMemcpyDeviceToHost, s));
         HIPCHECK(hipStreamSynchronize(s));
+        AmrBases ab;
+        for (int l = 0; l < 16; ++l) ab.b[l] = 0u;
         for (int l = 1; l <= max_level; ++l) hb[l] = hb[l - 1] + hc[l - 1];
-        HIPCHECK(hipMemcpyAsync(bases, hb, sizeof hb, hipMemcpyHostToDevice, s));
-        hipLaunchKernelGGL(k_amr_scatter<T>, dim3(nb256), dim3(256), 0, s, pin, (const uint8_t *)lv, cursor,
-                           (const unsigned *)bases, simp, rho);
-        HIPCHECK(hipStreamSynchronize(s));  // bases[] is read from host memory above
+        for (int l = 0; l <= max_level; ++l) ab.b[l] = hb[l];
+        hipLaunchKernelGGL(k_amr_scatter<T>, dim3(nb256), dim3(256), 0, s, pin, (const uint8_t *)lv, cursor, ab, simp,
+                           rho);
     }
     // one problem per projection level, in mass units (level 0 writes the
     // caller's grid), projected in one batched launch; all levels add to the

@@ -337,9 +337,11 @@ struct Poly3 {
     // Keep the part with x_ax >= c (keep_upper) or x_ax < c.  Returns false
     // when the vertex capacity would be exceeded or the graph is not a valid
     // polytope graph (the polytope is then left unusable).
-    SP_HD bool clip(int ax, T c, bool keep_upper)
+    SP_HD bool clip(int ax, T c, bool keep_upper) { return clip_classified(ax, c, keep_upper, below_mask(ax, c)); }
+
+    // The same with the live vertices below the plane already known.
+    SP_HD bool clip_classified(int ax, T c, bool keep_upper, uint32_t below)
     {
-        uint32_t below = below_mask(ax, c);
         uint32_t keep = keep_upper ? (live & ~below) : below;
         if (keep == live) return true;
         if (keep == 0u) {
@@ -433,12 +435,16 @@ struct Poly3 {
     // whole polytope when whole is true).  Returns 6*volume in s6 and
     // 24*integral in s24.  Returns false if the walk does not close (a
     // corrupted graph).
-    SP_HD bool integrate_below(int ax, T c, bool whole, T &s6, T &s24) const
+    //
+    // below_out (optional): the live vertices below the plane (when whole is
+    // false), for a cut at the same plane.
+    SP_HD bool integrate_below(int ax, T c, bool whole, T &s6, T &s24, uint32_t *below_out = nullptr) const
     {
         s6 = T(0);
         s24 = T(0);
-        if (live == 0u) return true;
         uint32_t below = whole ? live : below_mask(ax, c);
+        if (below_out) *below_out = below;
+        if (live == 0u) return true;
         if (below == 0u) return true;
         if (below == live) whole = true;
         S4<T> A = V(lowbit(live));

@@ -558,11 +558,13 @@ struct Sweep3 {
         fail[0] = cx;
         fail[1] = cy;
         fail[2] = iz;
-        if (!P.integrate_below(2, (T)(iz + 1 - zo), last, s6, s24)) return -1;
+        uint32_t below = 0u;
+        if (!P.integrate_below(2, (T)(iz + 1 - zo), last, s6, s24, &below)) return -1;
         if (s24 != T(0)) dep(cx, cy, iz, s24 / T(24));
         if (!last) {
             fail[2] = iz + 1;
-            if (!P.clip(2, (T)(iz + 1 - zo), true)) return -1;
+            // (the integral classified the vertices against the same plane)
+            if (!P.clip_classified(2, (T)(iz + 1 - zo), true, below)) return -1;
             ++iz;
             if (P.empty()) zhi = iz - 1;
         } else {
