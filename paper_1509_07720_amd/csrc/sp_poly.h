@@ -501,6 +501,10 @@ struct Poly3 {
             cnt += valid ? 1 : 0;
         };
         const int steps = 3 * __builtin_popcount(live);
+        // (three steps per trip: the walk state rotates through registers
+        // instead of being copied at every back-edge; 44.5 -> 43.2 ms on the
+        // soup, 2 and 4 measured in between)
+#pragma unroll 3
         for (int it = 0; it < steps; ++it) {
             if (!open) {
                 const uint32_t any = (un0 | un1 | un2) & below;
