@@ -237,7 +237,7 @@ sp_status sp_project_tets_corners(sp_ctx *ctx, const sp_problem *prob, void *str
  * difference (or sum) of the two density functions.  The pieces of such
  * simplices take the cell centre as their common origin.  Facets are matched
  * on the device by their vertex indices (a hash table in the context's
- * scratch, about 76 bytes per simplex); a facet met by more than two
+ * scratch, 76 to 108 bytes per simplex); a facet met by more than two
  * simplices is paired once and its other simplices sum it alone.  The same
  * result as sp_project_tets_corners up to rounding (tested to 1e-12 of each
  * cell's coverage scale); n_simplex below 2^30 (else SP_E_INVALID_ARG).
