@@ -331,7 +331,9 @@ typedef struct {
     double ms_clip;          /* clip-integrate-deposit over all work items          */
     double ms_clip_retry;    /* items resumed with larger polytopes                 */
     double ms_finalize;      /* hi+lo merge and total-mass reduction                */
-    long long pieces;        /* pieces deposited by the last call (mode 2 only)     */
+    long long pieces;        /* pieces deposited by the last call (mode 2 only);    */
+                             /* for the corner sums, the grid deposits (one per    */
+                             /* piece vertex and cell)                             */
     long long items;         /* work items of the last call                         */
     int clip_blocks;         /* persistent blocks of the last call's clip launch    */
 } sp_profile;

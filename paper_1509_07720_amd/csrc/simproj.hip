@@ -1091,7 +1091,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
             auto dep = make_dep<double>(p, L, kIdentity);
             FacetFuse fz;
             if constexpr (FUSED) corner_fuse(p, f, s, L, sw, fz);
-            if (corner_project(L, dep, FUSED ? &fz : nullptr) > 0) {
+            const int big = corner_project(L, dep, FUSED ? &fz : nullptr);
+            // counting runs only: grid deposits (one per vertex and cell with terms)
+            if (p.count_pieces && dep.count) atomicAdd(&p.cs->pieces, (unsigned long long)dep.count);
+            if (big > 0) {
                 record_error(p.es, SP_E_UNSUPPORTED);
                 atomicAdd(&p.es->n_degenerate, 1);
             }

@@ -134,3 +134,23 @@ def test_fused_on_a_folded_sheet_and_repeated_calls(ctx):
         err = oracle.cell_error(g.cpu().numpy(), oracle.project(prob))
         print("folded/fused", err, flush=True)
         assert err["e_cell"] <= TOL_CELL and err["e_mass"] <= TOL_MASS, err
+
+
+def test_fused_terms_reach_the_grid_less_often(ctx):
+    """The facet matching finds the shared facets on the device: with the
+    pairs summed once, fewer vertices deposit terms than without fusion (a
+    corner of the mesh whose three facets are all summed by neighbours of
+    lower index deposits nothing); deposits counted in profiling mode 2."""
+    prob = synth.zeldovich_3d(n=12, grid=24, sigma_cells=1.5, seed=2)
+    x, s, r = _dev(prob)
+    counts = []
+    for fused in (False, True):
+        assert simproj.sp_profile_enable(ctx.handle, 2) == simproj.SP_OK
+        ctx.project_corners(x, s, r, [24] * 3, out_mass=True, fused=fused)
+        assert ctx.sync_status() == simproj.SP_OK, simproj.sp_last_error()
+        st, prof = simproj.sp_profile_read(ctx.handle)
+        assert st == simproj.SP_OK
+        counts.append(int(prof.pieces))
+        assert simproj.sp_profile_enable(ctx.handle, 0) == simproj.SP_OK
+    print("deposits plain/fused", counts, flush=True)
+    assert 0 < counts[1] < counts[0], counts
