@@ -108,7 +108,8 @@ struct Tuning {
 };
 
 // Expected pieces per work item: one lane's expected share of the launch
-// (16 pieces per simplex assumed, 9 waves of 64 lanes per CU), within
+// (16 pieces per simplex assumed, a nominal 9 waves of 64 lanes per CU: the
+// sizes for the 11 waves that run measured the same), within
 // [16, 1024].  Few simplices (big ones, as a rule) are cut into many items
 // so that every lane has work; many small ones stay whole, which saves the
 // per-item set-up and column rebuilds.
