@@ -160,7 +160,7 @@ def test_repeated_calls_agree(ctx, prec):
     varies), but repeated calls on the same input agree to the rounding of
     that order: 1e-15 (FP64) and 1e-6 (FP32C) of the largest cell, and the
     piece count is the same."""
-    prob = synth.tet_soup(n_tets=200_000, grid=128, seed=11)
+    prob = synth.tet_soup(n_tets=200_000, grid=256, seed=11)
     if prec == "fp32c":
         prob = synth.as_float32(prob)
     grids = [run(ctx, prob, prec)[0] for _ in range(3)]
