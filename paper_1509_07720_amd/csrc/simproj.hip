@@ -61,7 +61,8 @@ constexpr int CLS_WIDE = NCLS - 1;
 // share a CU when the kernel keeps to 168 VGPRs (3 waves per SIMD); the
 // kernel is latency bound, and every wave counts (9 waves ran 9 % faster
 // than 8).  No 10M-tet soup item needed more than 14; one that does is
-// finished by the 32-slot kernel.  FP64 (32-byte slots): 15 slots, 5 waves.
+// finished by the 32-slot kernel.  FP64 (28 bytes a slot, positions and
+// neighbour words apart): 15 slots, 6 waves.
 template <typename T>
 constexpr int maxv3() { return sizeof(T) == 4 ? 14 : 15; }
 constexpr int MAXV3_BIG = 32;
@@ -694,7 +695,13 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(clip_waves_p
     constexpr bool WIDE = sizeof(T) == 8 && sizeof(TI) == 4;
     const ProbDev<TI> &p = p0;  // fields shared by every problem of the launch
     constexpr int SLOTS = D == 3 ? MAXV : 2 * MAXP2;
-    __shared__ V4<T> s_p[SLOTS][WG];  // 3D: polytope slots (S4, same size); 2D: polygon buffers
+    // 3D FP32: polytope slots (S4, the size of V4); 3D FP64: positions, then
+    // neighbour words (28 bytes a slot); 2D: polygon buffers
+    constexpr bool SPLIT = D == 3 && sizeof(T) == 8;
+    constexpr size_t LDS_BYTES =
+        SPLIT ? (size_t)MAXV * WG * (sizeof(P3D) + sizeof(uint32_t)) : (size_t)SLOTS * WG * sizeof(V4<T>);
+    __shared__ __attribute__((aligned(16))) unsigned char s_raw[LDS_BYTES];
+    V4<T>(*s_p)[WG] = reinterpret_cast<V4<T>(*)[WG]>(s_raw);
     const int lane = threadIdx.x;
     const unsigned total = overflow_pass ? min(p.cs->ovf_count, (unsigned)OVF_CAP)
                                          : (WIDE ? p.cs->hist[CLS_WIDE] : p.cs->total);
@@ -705,6 +712,10 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(clip_waves_p
     bool q_done = false;
     Poly3<T, MAXV, WG> P3;
     P3.p = reinterpret_cast<S4<T> *>(&s_p[0][lane]);
+    if constexpr (SPLIT) {
+        P3.pd = reinterpret_cast<P3D *>(s_raw) + lane;
+        P3.pn = reinterpret_cast<uint32_t *>(s_raw + (size_t)MAXV * WG * sizeof(P3D)) + lane;
+    }
     P3.live = 0u;
     Poly2<T, MAXP2, WG> P2;
     P2.a = &s_p[0][lane];

@@ -146,6 +146,13 @@ struct alignas(sizeof(T) * 4) S4 {
 static_assert(sizeof(S4<float>) == sizeof(V4<float>) && sizeof(S4<double>) == sizeof(V4<double>),
               "polytope slots and polygon vertices share one LDS buffer");
 
+// FP64 polytopes keep positions (24 bytes) and neighbour words (4 bytes) in
+// two arrays: 28 bytes a slot instead of 32, which lets 6 waves share a CU
+// instead of 5.
+struct alignas(8) P3D {
+    double x, y, z;
+};
+
 // Point where segment (a, b) meets the plane x_ax = c, for a strictly below
 // and b at or above the plane; the same rule as isect (nearer end, exact
 // coordinate along ax), positions only.
@@ -203,7 +210,10 @@ template <typename T, int MAXV, int STRIDE>
 struct Poly3 {
     static_assert(MAXV <= 32, "vertex masks are 32-bit");
     static constexpr uint32_t SLOTS = MAXV == 32 ? 0xffffffffu : ((1u << MAXV) - 1u);
-    S4<T> *p;
+    static constexpr bool SPLIT = sizeof(T) == 8;
+    S4<T> *p;        // FP32: one record per slot
+    P3D *pd;         // FP64: positions
+    uint32_t *pn;    // FP64: neighbour words
     uint32_t live;
     // density rho(q) = r0 + g . (q - o) of the simplex being swept; gd is
     // the gradient in double precision (for the one evaluation per piece
@@ -217,14 +227,48 @@ struct Poly3 {
     T o[3];
     T rlo, rhi;
 
-    SP_HD S4<T> V(int v) const { return p[v * STRIDE]; }
-    SP_HD void setV(int v, const S4<T> &q) { p[v * STRIDE] = q; }
-    SP_HD uint32_t N(int v) const { return (uint32_t)p[v * STRIDE].nb; }
-    SP_HD void setN(int v, uint32_t x) { p[v * STRIDE].nb = x; }
+    SP_HD S4<T> V(int v) const
+    {
+        if constexpr (SPLIT) {
+            const P3D q = pd[v * STRIDE];
+            S4<T> r;
+            r.x = q.x;
+            r.y = q.y;
+            r.z = q.z;
+            r.nb = pn[v * STRIDE];
+            return r;
+        } else {
+            return p[v * STRIDE];
+        }
+    }
+    SP_HD void setV(int v, const S4<T> &q)
+    {
+        if constexpr (SPLIT) {
+            pd[v * STRIDE] = P3D{(double)q.x, (double)q.y, (double)q.z};
+            pn[v * STRIDE] = (uint32_t)q.nb;
+        } else {
+            p[v * STRIDE] = q;
+        }
+    }
+    SP_HD uint32_t N(int v) const
+    {
+        if constexpr (SPLIT) return pn[v * STRIDE];
+        else return (uint32_t)p[v * STRIDE].nb;
+    }
+    SP_HD void setN(int v, uint32_t x)
+    {
+        if constexpr (SPLIT) pn[v * STRIDE] = x;
+        else p[v * STRIDE].nb = x;
+    }
     SP_HD T coord(int v, int ax) const
     {
-        const T *q = reinterpret_cast<const T *>(&p[v * STRIDE]);
-        return q[ax];
+        if constexpr (SPLIT) {
+            const double *q = reinterpret_cast<const double *>(&pd[v * STRIDE]);
+            return (T)q[ax];
+        } else {
+            const T *q = reinterpret_cast<const T *>(&p[v * STRIDE]);
+            return q[ax];
+        }
     }
     SP_HD bool empty() const { return live == 0u; }
 
@@ -304,7 +348,7 @@ struct Poly3 {
     {
 #pragma unroll
         for (int v = 0; v < MAXV; ++v) {
-            T *q = reinterpret_cast<T *>(&p[v * STRIDE]);
+            T *q = SPLIT ? reinterpret_cast<T *>(&pd[v * STRIDE]) : reinterpret_cast<T *>(&p[v * STRIDE]);
             q[ax] -= d;
         }
         o[ax] -= d;
