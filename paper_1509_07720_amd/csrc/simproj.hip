@@ -57,12 +57,13 @@ constexpr int WIDE_SPAN = 64;
 constexpr int CLS_WIDE = NCLS - 1;
 // Polytope vertex slots per lane.  A cut frees the removed vertices it no
 // longer reads before it places new ones, so its peak stays near the larger
-// of the two polytopes.  FP32: 14 slots (14 KB of LDS per wave) let 11 waves
+// of the two polytopes.  FP32: 14 slots (12.3 KB of LDS per wave) let 12 waves
 // share a CU when the kernel keeps to 168 VGPRs (3 waves per SIMD); the
 // kernel is latency bound, and every wave counts (9 waves ran 9 % faster
 // than 8).  No 10M-tet soup item needed more than 14; one that does is
-// finished by the 32-slot kernel.  FP64 (28 bytes a slot, positions and
-// neighbour words apart): 15 slots, 6 waves.
+// finished by the 32-slot kernel.  FP64: 15 slots, 6 waves.  (A slot is
+// 12 + 2 bytes in FP32 and 24 + 4 in FP64: positions and neighbour words
+// in separate arrays.)
 template <typename T>
 constexpr int maxv3() { return sizeof(T) == 4 ? 14 : 15; }
 constexpr int MAXV3_BIG = 32;
@@ -695,11 +696,10 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(clip_waves_p
     constexpr bool WIDE = sizeof(T) == 8 && sizeof(TI) == 4;
     const ProbDev<TI> &p = p0;  // fields shared by every problem of the launch
     constexpr int SLOTS = D == 3 ? MAXV : 2 * MAXP2;
-    // 3D FP32: polytope slots (S4, the size of V4); 3D FP64: positions, then
-    // neighbour words (28 bytes a slot); 2D: polygon buffers
-    constexpr bool SPLIT = D == 3 && sizeof(T) == 8;
+    // 3D: polytope positions, then neighbour words; 2D: polygon buffers
     constexpr size_t LDS_BYTES =
-        SPLIT ? (size_t)MAXV * WG * (sizeof(P3D) + sizeof(uint32_t)) : (size_t)SLOTS * WG * sizeof(V4<T>);
+        D == 3 ? (size_t)MAXV * WG * (sizeof(P3T<T>) + sizeof(typename NbStore<T>::type))
+               : (size_t)SLOTS * WG * sizeof(V4<T>);
     __shared__ __attribute__((aligned(16))) unsigned char s_raw[LDS_BYTES];
     V4<T>(*s_p)[WG] = reinterpret_cast<V4<T>(*)[WG]>(s_raw);
     const int lane = threadIdx.x;
@@ -711,10 +711,9 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(clip_waves_p
     unsigned q_base = 0u, q_n = 0u, q_h = 0u;  // current chunk [q_base, q_base + q_n), next unclaimed q_h
     bool q_done = false;
     Poly3<T, MAXV, WG> P3;
-    P3.p = reinterpret_cast<S4<T> *>(&s_p[0][lane]);
-    if constexpr (SPLIT) {
-        P3.pd = reinterpret_cast<P3D *>(s_raw) + lane;
-        P3.pn = reinterpret_cast<uint32_t *>(s_raw + (size_t)MAXV * WG * sizeof(P3D)) + lane;
+    if constexpr (D == 3) {
+        P3.pp = reinterpret_cast<P3T<T> *>(s_raw) + lane;
+        P3.pn = reinterpret_cast<typename NbStore<T>::type *>(s_raw + (size_t)MAXV * WG * sizeof(P3T<T>)) + lane;
     }
     P3.live = 0u;
     Poly2<T, MAXP2, WG> P2;

@@ -110,21 +110,22 @@ SP_HD inline V4<T> isect(const V4<T> &a, const V4<T> &b, int ax, T c)
     return q;
 }
 
-SP_HD inline int nbr(uint32_t nb, int i) { return (int)((nb >> (8 * i)) & 0xffu); }
+// neighbour word: three 5-bit slot indices (at most 32 slots), 15 bits
+SP_HD inline int nbr(uint32_t nb, int i) { return (int)((nb >> (5 * i)) & 31u); }
 SP_HD inline uint32_t set_nbr(uint32_t nb, int i, int v)
 {
-    return (nb & ~(0xffu << (8 * i))) | ((uint32_t)v << (8 * i));
+    return (nb & ~(31u << (5 * i))) | ((uint32_t)v << (5 * i));
 }
 SP_HD inline int slot_of(uint32_t nb, int v)
 {
     return nbr(nb, 0) == v ? 0 : (nbr(nb, 1) == v ? 1 : 2);
 }
-SP_HD inline uint32_t pack3(int a, int b, int c) { return (uint32_t)a | ((uint32_t)b << 8) | ((uint32_t)c << 16); }
+SP_HD inline uint32_t pack3(int a, int b, int c) { return (uint32_t)a | ((uint32_t)b << 5) | ((uint32_t)c << 10); }
 SP_HD inline int lowbit(uint32_t m) { return __builtin_ctz(m); }
 
-// A polytope vertex slot: position and the packed neighbour word in one
-// 16-byte (FP32) or 32-byte (FP64) record, so that a walk step reads both
-// with one load.  The density is not stored per vertex: over a simplex it
+// A polytope vertex as the walks hold it in registers: position and the
+// packed neighbour word (in LDS the two live in separate arrays, below).
+// The density is not stored per vertex: over a simplex it
 // is an affine function of position (set once per simplex in the polytope),
 // evaluated where an integral needs it.
 template <typename T>
@@ -146,11 +147,23 @@ struct alignas(sizeof(T) * 4) S4 {
 static_assert(sizeof(S4<float>) == sizeof(V4<float>) && sizeof(S4<double>) == sizeof(V4<double>),
               "polytope slots and polygon vertices share one LDS buffer");
 
-// FP64 polytopes keep positions (24 bytes) and neighbour words (4 bytes) in
-// two arrays: 28 bytes a slot instead of 32, which lets 6 waves share a CU
-// instead of 5.
-struct alignas(8) P3D {
-    double x, y, z;
+// In LDS a polytope keeps its positions (3 T) and its neighbour words in
+// two arrays: 12 + 2 bytes a slot in FP32 (12 resident waves per CU instead
+// of 11 with 16-byte records) and 24 + 4 in FP64 (6 instead of 5 with
+// 32-byte records; 16-bit words measured 3 % slower there).
+template <typename T>
+struct P3T {
+    T x, y, z;
+};
+template <typename T>
+struct NbStore;
+template <>
+struct NbStore<float> {
+    using type = uint16_t;
+};
+template <>
+struct NbStore<double> {
+    using type = uint32_t;
 };
 
 // Point where segment (a, b) meets the plane x_ax = c, for a strictly below
@@ -210,10 +223,9 @@ template <typename T, int MAXV, int STRIDE>
 struct Poly3 {
     static_assert(MAXV <= 32, "vertex masks are 32-bit");
     static constexpr uint32_t SLOTS = MAXV == 32 ? 0xffffffffu : ((1u << MAXV) - 1u);
-    static constexpr bool SPLIT = sizeof(T) == 8;
-    S4<T> *p;        // FP32: one record per slot
-    P3D *pd;         // FP64: positions
-    uint32_t *pn;    // FP64: neighbour words
+    using NbW = typename NbStore<T>::type;
+    P3T<T> *pp;      // positions
+    NbW *pn;         // neighbour words
     uint32_t live;
     // density rho(q) = r0 + g . (q - o) of the simplex being swept; gd is
     // the gradient in double precision (for the one evaluation per piece
@@ -229,46 +241,25 @@ struct Poly3 {
 
     SP_HD S4<T> V(int v) const
     {
-        if constexpr (SPLIT) {
-            const P3D q = pd[v * STRIDE];
-            S4<T> r;
-            r.x = q.x;
-            r.y = q.y;
-            r.z = q.z;
-            r.nb = pn[v * STRIDE];
-            return r;
-        } else {
-            return p[v * STRIDE];
-        }
+        const P3T<T> q = pp[v * STRIDE];
+        S4<T> r;
+        r.x = q.x;
+        r.y = q.y;
+        r.z = q.z;
+        r.nb = pn[v * STRIDE];
+        return r;
     }
     SP_HD void setV(int v, const S4<T> &q)
     {
-        if constexpr (SPLIT) {
-            pd[v * STRIDE] = P3D{(double)q.x, (double)q.y, (double)q.z};
-            pn[v * STRIDE] = (uint32_t)q.nb;
-        } else {
-            p[v * STRIDE] = q;
-        }
+        pp[v * STRIDE] = P3T<T>{q.x, q.y, q.z};
+        pn[v * STRIDE] = (NbW)q.nb;
     }
-    SP_HD uint32_t N(int v) const
-    {
-        if constexpr (SPLIT) return pn[v * STRIDE];
-        else return (uint32_t)p[v * STRIDE].nb;
-    }
-    SP_HD void setN(int v, uint32_t x)
-    {
-        if constexpr (SPLIT) pn[v * STRIDE] = x;
-        else p[v * STRIDE].nb = x;
-    }
+    SP_HD uint32_t N(int v) const { return pn[v * STRIDE]; }
+    SP_HD void setN(int v, uint32_t x) { pn[v * STRIDE] = (NbW)x; }
     SP_HD T coord(int v, int ax) const
     {
-        if constexpr (SPLIT) {
-            const double *q = reinterpret_cast<const double *>(&pd[v * STRIDE]);
-            return (T)q[ax];
-        } else {
-            const T *q = reinterpret_cast<const T *>(&p[v * STRIDE]);
-            return q[ax];
-        }
+        const T *q = reinterpret_cast<const T *>(&pp[v * STRIDE]);
+        return q[ax];
     }
     SP_HD bool empty() const { return live == 0u; }
 
@@ -348,7 +339,7 @@ struct Poly3 {
     {
 #pragma unroll
         for (int v = 0; v < MAXV; ++v) {
-            T *q = SPLIT ? reinterpret_cast<T *>(&pd[v * STRIDE]) : reinterpret_cast<T *>(&p[v * STRIDE]);
+            T *q = reinterpret_cast<T *>(&pp[v * STRIDE]);
             q[ax] -= d;
         }
         o[ax] -= d;

@@ -41,9 +41,11 @@ struct HostDep {
 template <int MAXV>
 bool sweep_from(const Local<float> &L, int sb, int sc, int ry, HostDep &dep, int *fail)
 {
-    static S4<float> slots[MAXV];
+    static P3T<float> pos[MAXV];
+    static uint16_t nbw[MAXV];
     Poly3<float, MAXV, 1> P;
-    P.p = slots;
+    P.pp = pos;
+    P.pn = nbw;
     P.live = 0u;
     return sweep3<float, MAXV, 1>(P, L, sb, sc, dep, ry, fail);
 }

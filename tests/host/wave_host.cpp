@@ -62,7 +62,8 @@ extern "C" int wave_host(const float *xyz, int64_t n_vert, const int32_t *simp, 
     const long stride[3] = {1, (long)dims[0], (long)dims[0] * dims[1]};
     for (int k = 0; k < 7; ++k) stats[k] = 0;
     static wv::GroupLDS sh;
-    static S4<float> slots[32];
+    static P3T<float> pos[32];
+    static uint16_t nbw[32];
     for (int64_t s = 0; s < n; ++s) {
         Local<float> L0;
         double ex0[4][3], ex[4][3];
@@ -121,7 +122,8 @@ extern "C" int wave_host(const float *xyz, int64_t n_vert, const int32_t *simp, 
             d2.suppress_iy = S.fail[1];
             d2.suppress_iz = S.fail[2];
             Poly3<float, 32, 1> P;
-            P.p = slots;
+            P.pp = pos;
+            P.pn = nbw;
             P.live = 0u;
             int fail2[3];
             if (!sweep3<float, 32, 1>(P, L, S.fail[0], sb + sc - S.fail[0], d2, S.fail[1], fail2)) stats[4]++;
