@@ -110,17 +110,30 @@ SP_HD inline V4<T> isect(const V4<T> &a, const V4<T> &b, int ax, T c)
     return q;
 }
 
-// neighbour word: three 5-bit slot indices (at most 32 slots), 15 bits
-SP_HD inline int nbr(uint32_t nb, int i) { return (int)((nb >> (5 * i)) & 31u); }
+// neighbour word: three slot indices of B bits each (B >= 5: at most 32
+// slots).  FP32 polytopes use B = 5 (15 bits, stored as 16-bit words);
+// FP64 ones B = 8, whose byte fields the hardware extracts and inserts
+// without a separate bit-field instruction.
+template <int B>
+SP_HD inline int nbr(uint32_t nb, int i)
+{
+    return (int)((nb >> (B * i)) & ((1u << B) - 1u));
+}
+template <int B>
 SP_HD inline uint32_t set_nbr(uint32_t nb, int i, int v)
 {
-    return (nb & ~(31u << (5 * i))) | ((uint32_t)v << (5 * i));
+    return (nb & ~(((1u << B) - 1u) << (B * i))) | ((uint32_t)v << (B * i));
 }
+template <int B>
 SP_HD inline int slot_of(uint32_t nb, int v)
 {
-    return nbr(nb, 0) == v ? 0 : (nbr(nb, 1) == v ? 1 : 2);
+    return nbr<B>(nb, 0) == v ? 0 : (nbr<B>(nb, 1) == v ? 1 : 2);
 }
-SP_HD inline uint32_t pack3(int a, int b, int c) { return (uint32_t)a | ((uint32_t)b << 5) | ((uint32_t)c << 10); }
+template <int B>
+SP_HD inline uint32_t pack3(int a, int b, int c)
+{
+    return (uint32_t)a | ((uint32_t)b << B) | ((uint32_t)c << (2 * B));
+}
 SP_HD inline int lowbit(uint32_t m) { return __builtin_ctz(m); }
 
 // A polytope vertex as the walks hold it in registers: position and the
@@ -160,10 +173,12 @@ struct NbStore;
 template <>
 struct NbStore<float> {
     using type = uint16_t;
+    static constexpr int bits = 5;
 };
 template <>
 struct NbStore<double> {
     using type = uint32_t;
+    static constexpr int bits = 8;
 };
 
 // Point where segment (a, b) meets the plane x_ax = c, for a strictly below
@@ -224,6 +239,7 @@ struct Poly3 {
     static_assert(MAXV <= 32, "vertex masks are 32-bit");
     static constexpr uint32_t SLOTS = MAXV == 32 ? 0xffffffffu : ((1u << MAXV) - 1u);
     using NbW = typename NbStore<T>::type;
+    static constexpr int NB = NbStore<T>::bits;
     P3T<T> *pp;      // positions
     NbW *pn;         // neighbour words
     uint32_t live;
@@ -303,7 +319,7 @@ struct Poly3 {
     // A positively oriented tetrahedron (det(v1-v0, v2-v0, v3-v0) > 0).
     SP_HD void init_tet(const V4<T> *v)
     {
-        const uint32_t nbs[4] = {pack3(1, 3, 2), pack3(2, 3, 0), pack3(0, 3, 1), pack3(1, 2, 0)};
+        const uint32_t nbs[4] = {pack3<NB>(1, 3, 2), pack3<NB>(2, 3, 0), pack3<NB>(0, 3, 1), pack3<NB>(1, 2, 0)};
         for (int i = 0; i < 4; ++i) {
             S4<T> q;
             q.x = v[i].x;
@@ -394,7 +410,7 @@ struct Poly3 {
             for (uint32_t w = gone; w; w &= w - 1u) {
                 const int x = lowbit(w);
                 const uint32_t nbx = N(x);
-                if (!(((keep >> nbr(nbx, 0)) | (keep >> nbr(nbx, 1)) | (keep >> nbr(nbx, 2))) & 1u)) inner |= 1u << x;
+                if (!(((keep >> nbr<NB>(nbx, 0)) | (keep >> nbr<NB>(nbx, 1)) | (keep >> nbr<NB>(nbx, 2))) & 1u)) inner |= 1u << x;
             }
             freem |= inner;
             gone &= ~inner;
@@ -410,7 +426,7 @@ struct Poly3 {
             const S4<T> px = V(x);
             const uint32_t nbx = (uint32_t)px.nb;
             // the three neighbours are read together up front
-            const int v3[3] = {nbr(nbx, 0), nbr(nbx, 1), nbr(nbx, 2)};
+            const int v3[3] = {nbr<NB>(nbx, 0), nbr<NB>(nbx, 1), nbr<NB>(nbx, 2)};
             const S4<T> pv3[3] = {V(v3[0]), V(v3[1]), V(v3[2])};
             bool reused = false;
 #pragma unroll
@@ -428,11 +444,11 @@ struct Poly3 {
                 }
                 fresh |= 1u << u;
                 S4<T> q = keep_upper ? isect3(px, pv3[i], ax, c) : isect3(pv3[i], px, ax, c);
-                q.nb = pack3(v, v, v);
+                q.nb = pack3<NB>(v, v, v);
                 setV(u, q);
                 if (u != x) {
                     const uint32_t nbv = N(v);
-                    setN(v, set_nbr(nbv, slot_of(nbv, x), u));
+                    setN(v, set_nbr<NB>(nbv, slot_of<NB>(nbv, x), u));
                 }
             }
             if (!reused) freem |= 1u << x;
@@ -442,22 +458,22 @@ struct Poly3 {
         // over all walk steps keeps the lanes of a wave in step.
         uint32_t todo = fresh;
         int u = lowbit(todo);
-        int prev = u, cur = nbr(N(u), 0);
+        int prev = u, cur = nbr<NB>(N(u), 0);
         int guard = 0;
         while (todo) {
             uint32_t nbc = N(cur);
-            int j = slot_of(nbc, prev);
-            int nxt = nbr(nbc, (j + 1) % 3);
+            int j = slot_of<NB>(nbc, prev);
+            int nxt = nbr<NB>(nbc, (j + 1) % 3);
             prev = cur;
             cur = nxt;
             if ((fresh >> cur) & 1u) {
-                setN(u, set_nbr(N(u), 2, cur));
-                setN(cur, set_nbr(N(cur), 1, u));
+                setN(u, set_nbr<NB>(N(u), 2, cur));
+                setN(cur, set_nbr<NB>(N(cur), 1, u));
                 todo &= todo - 1u;
                 if (todo) {
                     u = lowbit(todo);
                     prev = u;
-                    cur = nbr(N(u), 0);
+                    cur = nbr<NB>(N(u), 0);
                 }
             }
             if (++guard > 4 * MAXV * MAXV) return false;
@@ -490,7 +506,7 @@ struct Poly3 {
                 const S4<T> pv = V(v);
                 const uint32_t nbv = (uint32_t)pv.nb;
                 for (int i = 0; i < 3; ++i) {
-                    const int x = nbr(nbv, i);
+                    const int x = nbr<NB>(nbv, i);
                     if (!((below >> x) & 1u)) {
                         A = isect3(pv, V(x), ax, c);
                         found = true;
@@ -560,7 +576,7 @@ struct Poly3 {
             un2 &= pc == 2 ? ~bit : ~0u;
             // the neighbour word of the current vertex comes with its
             // position, so each step waits for one LDS read
-            const int vnext = nbr(ncur, pc);
+            const int vnext = nbr<NB>(ncur, pc);
             const S4<T> b = V(vnext);
             const uint32_t nnext = (uint32_t)b.nb;
             const bool bb = (below >> vnext) & 1u;
@@ -576,7 +592,7 @@ struct Poly3 {
             hi.z = ba ? b.z : a.z;
             acc(isect3(lo, hi, ax, c), ba != bb);
             open = vnext != vs;
-            const int np = slot_of(nnext, vcur);
+            const int np = slot_of<NB>(nnext, vcur);
             pc = np == 2 ? 0 : np + 1;
             vcur = vnext;
             a = b;
