@@ -54,7 +54,15 @@
  * drops them).  The environment variable SP_SCRATCH_CAP (bytes, with an
  * optional K, M or G suffix), read by sp_create, bounds the device memory a
  * context holds; a call that would need more returns SP_E_NO_MEMORY before
- * it enqueues anything, and the context stays usable.
+ * it enqueues anything, and the context stays usable.  Also read by
+ * sp_create, each choosing a context's kernels or initial launch
+ * parameters without changing results beyond rounding: SIMPROJ_SLAB_GROUP,
+ * SIMPROJ_ITEM_PIECES, SIMPROJ_CLIP_BLOCKS_PER_CU (launch parameters, as
+ * sp_tuning_set sets them), SIMPROJ_GROUP_CLIP=1 (FP32 3D clipping with one
+ * polytope per 16 lanes) and SIMPROJ_TILED_DEPOSIT=1 (single FP32 3D
+ * problems deposit through a per-wave cell tile in LDS, the per-thread
+ * contribution buffers of Section 3.5; both measured slower than the
+ * defaults).
  */
 #ifndef SIMPROJ_H
 #define SIMPROJ_H

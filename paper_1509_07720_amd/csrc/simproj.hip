@@ -73,6 +73,8 @@ constexpr int OVF_CAP = 1 << 20;  // overflow records per launch (24 MB of scrat
 // on the 10M-tet soup 40 measured best among 16..48 and among thresholds
 // relative to the busy lanes (the clip 10 % faster than building at once).
 constexpr int BUILD_MIN = 40;
+// Cells in a wave's deposit tile (the opt-in tiled FP32 clip kernel).
+constexpr int DEP_TILE = 64;
 
 // Per-call device state, cleared at the start of every call.
 struct CallState {
@@ -111,7 +113,8 @@ struct Tuning {
 
 // Expected pieces per work item: one lane's expected share of the launch
 // (16 pieces per simplex assumed, a nominal 9 waves of 64 lanes per CU: the
-// sizes for the 11 waves that run measured the same), within
+// sizes for the waves that actually run, 11 when measured, gave the same
+// times), within
 // [16, 1024].  Few simplices (big ones, as a rule) are cut into many items
 // so that every lane has work; many small ones stay whole, which saves the
 // per-item set-up and column rebuilds.
@@ -145,6 +148,12 @@ struct DepF32 {
     float scale;
     int suppress_iy, suppress_iz, suppress_ix;  // resume: skip pieces before this one
     int count;
+    // Optional per-wave deposit tile in LDS (the tiled instance of the FP32
+    // clip kernel; null otherwise): DEP_TILE cells of (key, hi, lo) in
+    // which pieces of one cell merge before one compensated grid deposit.
+    uint32_t *tkey;
+    float *thi, *tlo;
+    static constexpr uint32_t TILE_EMPTY = 0xffffffffu;
 
     // a piece computed in FP64 (a simplex routed to FP64)
     __device__ void operator()(int ix, int iy, int iz, double v)
@@ -164,11 +173,54 @@ struct DepF32 {
         if (!cell(ix, iy, iz, idx)) return;
         float x = v * scale;
         if (cmax) atomicMax(cmax + idx, __float_as_uint(fabsf(x)));
+        if (tkey && tile_add(idx, x)) return;
         float old = unsafeAtomicAdd(hi + idx, x);
         float s = old + x;
         float bb = s - old;
         float err = (old - (s - bb)) + (x - bb);
         if (err != 0.0f) unsafeAtomicAdd(lo + idx, err);
+    }
+
+    // Grid deposit of a merged cell: its high part with the compensated
+    // add; the rounding error and its low part go to the low grid.
+    static __device__ void flush(float *hi, float *lo, size_t idx, float h, float l)
+    {
+#pragma clang fp contract(off)
+        float old = unsafeAtomicAdd(hi + idx, h);
+        float s = old + h;
+        float bb = s - old;
+        float err = (old - (s - bb)) + (h - bb) + l;
+        if (err != 0.0f) unsafeAtomicAdd(lo + idx, err);
+    }
+
+    // Piece x of cell idx (< TILE_EMPTY) into the wave's tile: added there
+    // (LDS atomics, with TwoSum into the entry's low part) when the cell
+    // holds its hashed slot, else the lane tries to take the slot over,
+    // flushing the cell it evicts.  False when another lane took the slot
+    // first: the caller deposits directly.  The lanes of the wave run this
+    // in lockstep; every add into a cell already in the tile is issued
+    // before any take-over, and LDS operations of a wave complete in order.
+    __device__ bool tile_add(size_t idx, float x) const
+    {
+#pragma clang fp contract(off)
+        const uint32_t key = (uint32_t)idx;
+        const uint32_t t = (key * 2654435761u) >> 26;  // multiplicative hash onto 64 slots
+        const uint32_t k = tkey[t];
+        const bool match = k == key;
+        if (match) {
+            float old = atomicAdd(thi + t, x);
+            float s = old + x;
+            float bb = s - old;
+            float err = (old - (s - bb)) + (x - bb);
+            if (err != 0.0f) atomicAdd(tlo + t, err);
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (match) return true;
+        if (atomicCAS(tkey + t, k, key) != k) return false;
+        const float oh = atomicExch(thi + t, x);
+        const float ol = atomicExch(tlo + t, 0.0f);
+        if (k != TILE_EMPTY) flush(hi, lo, (size_t)k, oh, ol);
+        return true;
     }
 
     // Global index of local cell (ix, iy, iz); false outside a non-periodic
@@ -391,6 +443,9 @@ __device__ inline DepF32 make_dep(const ProbDev<float> &p, const Local<TL> &L, c
     d.suppress_iy = 0;
     d.suppress_iz = 0;
     d.count = 0;
+    d.tkey = nullptr;
+    d.thi = nullptr;
+    d.tlo = nullptr;
     return d;
 }
 template <typename TL>
@@ -678,7 +733,7 @@ __global__ __launch_bounds__(256) void k_scatter(ProbDev<T> p0, Batch b)
 // performs one sweep step (a column build if due, then one piece).
 //
 // Waves per SIMD the compiler must leave room for: 3 (at most 168 VGPRs) for
-// the 14-slot FP32 polytopes, whose LDS admits 11 waves per CU; the other
+// the 14-slot FP32 polytopes, whose LDS admits 12 waves per CU; the other
 // forms are bound by their LDS to 2 or fewer anyway.
 template <int D, typename T, int MAXV>
 constexpr int clip_waves_per_simd() { return D == 3 && sizeof(T) == 4 && MAXV <= 17 ? 3 : 1; }
@@ -688,18 +743,27 @@ constexpr int clip_waves_per_simd() { return D == 3 && sizeof(T) == 4 && MAXV <=
 // it takes the CLS_WIDE items at the head of the list (one slab each, swept
 // with the simplex's longest axis outermost), and a polytope that outgrows
 // its slots there is an internal error (it runs with 32 slots).
-template <int D, typename T, int MAXV, bool SINGLE, typename TI = T>
+//
+// TILED (FP32 3D, one problem, the grid's cells numbered below 2^32 - 1, no
+// per-cell maximum recorded): pieces go through the wave's deposit tile
+// (DepF32::tile_add), 64 cells of 12 bytes after the polytopes (13,312
+// bytes a wave, which still lets 12 waves share a CU); each wave flushes
+// its tile when its work is done.
+template <int D, typename T, int MAXV, bool SINGLE, typename TI = T, bool TILED = false>
 __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(clip_waves_per_simd<D, T, MAXV>()))) void k_clip(
     ProbDev<TI> p0, Batch b, int overflow_pass)
 {
     static_assert(WG == 64, "the queue logic assumes one wave per block");
+    static_assert(!TILED || (D == 3 && sizeof(T) == 4 && sizeof(TI) == 4 && SINGLE && DEP_TILE == WG),
+                  "the deposit tile is for one FP32 3D problem, one entry per lane");
     constexpr bool WIDE = sizeof(T) == 8 && sizeof(TI) == 4;
     const ProbDev<TI> &p = p0;  // fields shared by every problem of the launch
     constexpr int SLOTS = D == 3 ? MAXV : 2 * MAXP2;
-    // 3D: polytope positions, then neighbour words; 2D: polygon buffers
-    constexpr size_t LDS_BYTES =
-        D == 3 ? (size_t)MAXV * WG * (sizeof(P3T<T>) + sizeof(typename NbStore<T>::type))
-               : (size_t)SLOTS * WG * sizeof(V4<T>);
+    // 3D: polytope positions, then neighbour words (then the deposit tile);
+    // 2D: polygon buffers
+    constexpr size_t POLY_BYTES = (size_t)MAXV * WG * (sizeof(P3T<T>) + sizeof(typename NbStore<T>::type));
+    constexpr size_t LDS_BYTES = D == 3 ? POLY_BYTES + (TILED ? (size_t)DEP_TILE * 12 : 0)
+                                        : (size_t)SLOTS * WG * sizeof(V4<T>);
     __shared__ __attribute__((aligned(16))) unsigned char s_raw[LDS_BYTES];
     V4<T>(*s_p)[WG] = reinterpret_cast<V4<T>(*)[WG]>(s_raw);
     const int lane = threadIdx.x;
@@ -716,6 +780,17 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(clip_waves_p
         P3.pn = reinterpret_cast<typename NbStore<T>::type *>(s_raw + (size_t)MAXV * WG * sizeof(P3T<T>)) + lane;
     }
     P3.live = 0u;
+    uint32_t *t_key = nullptr;
+    float *t_hi = nullptr, *t_lo = nullptr;
+    if constexpr (TILED) {
+        t_key = reinterpret_cast<uint32_t *>(s_raw + POLY_BYTES);
+        t_hi = reinterpret_cast<float *>(s_raw + POLY_BYTES + DEP_TILE * 4);
+        t_lo = reinterpret_cast<float *>(s_raw + POLY_BYTES + DEP_TILE * 8);
+        t_key[lane] = DepF32::TILE_EMPTY;
+        t_hi[lane] = 0.0f;
+        t_lo[lane] = 0.0f;
+        __builtin_amdgcn_wave_barrier();
+    }
     Poly2<T, MAXP2, WG> P2;
     P2.a = &s_p[0][lane];
     P2.b = &s_p[D == 3 ? 0 : MAXP2][lane];
@@ -791,6 +866,11 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(clip_waves_p
                 }
                 if (ok) {
                     dep = make_dep<T>(q, L, ord);
+                    if constexpr (TILED) {
+                        dep.tkey = t_key;
+                        dep.thi = t_hi;
+                        dep.tlo = t_lo;
+                    }
                     if (overflow_pass) {
                         dep.suppress_ix = sb;
                         dep.suppress_iy = ry;
@@ -851,6 +931,12 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(clip_waves_p
                 atomicAdd(&p.es->n_internal, 1);
             }
         }
+    }
+    if constexpr (TILED) {
+        // the wave's work is done: each lane flushes one tile entry
+        __builtin_amdgcn_wave_barrier();
+        const uint32_t k = t_key[lane];
+        if (k != DepF32::TILE_EMPTY) DepF32::flush(p0.out, p0.lo, (size_t)k, t_hi[lane], t_lo[lane]);
     }
 }
 
@@ -1708,6 +1794,7 @@ struct sp_ctx {
     Tuning tune;
     int profiling;
     int group_clip;  // 1: the FP32 3D clip runs one polytope per 16 lanes (k_clipw) instead of one per lane
+    int tiled_deposit;  // 1: single FP32 3D problems clip with the per-wave deposit tile
     int prof_calls;
     int last_clip_blocks;
     // (start, end) events per recorded stage and per whole call
@@ -1823,6 +1910,8 @@ extern "C" sp_status sp_create(int hip_device, sp_ctx **ctx)
     c->profiling = 0;
     c->group_clip = 0;
     if (const char *e = getenv("SIMPROJ_GROUP_CLIP")) c->group_clip = atoi(e) != 0;
+    c->tiled_deposit = 0;
+    if (const char *e = getenv("SIMPROJ_TILED_DEPOSIT")) c->tiled_deposit = atoi(e) != 0;
     c->prof_calls = 0;
     c->last_clip_blocks = 0;
     c->noalloc = nullptr;
@@ -2128,6 +2217,13 @@ static void enqueue(sp_ctx *ctx, const Prepared<T> *v, int nv, const Batch &b, i
         // faster with the run-time choice for both forms
         const bool one = fp32 && single;
         auto kclip = one ? k_clip<D, T, MAXV3, true> : k_clip<D, T, MAXV3, false>;
+        if constexpr (D == 3 && sizeof(T) == 4) {
+            // the deposit tile when asked for and the grid's cells fit its keys
+            // (it measured 7-8 % slower than direct deposits on the soup, the
+            // lattice and the refined mesh)
+            if (one && ctx->tiled_deposit && p0.cmax == nullptr && v[0].ncell < (size_t)DepF32::TILE_EMPTY)
+                kclip = k_clip<D, T, MAXV3, true, T, true>;
+        }
         auto kretry = D == 3 ? (one ? k_clip<D, T, MAXV3_BIG, true> : k_clip<D, T, MAXV3_BIG, false>) : kclip;
         // 3D FP32: the group kernel when asked for (it measured slower than
         // one polytope per lane on every workload tried)
