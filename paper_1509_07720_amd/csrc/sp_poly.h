@@ -428,29 +428,31 @@ struct Poly3 {
             // the three neighbours are read together up front
             const int v3[3] = {nbr<NB>(nbx, 0), nbr<NB>(nbx, 1), nbr<NB>(nbx, 2)};
             const S4<T> pv3[3] = {V(v3[0]), V(v3[1]), V(v3[2])};
-            bool reused = false;
+            // straight-line code with selects over the three neighbours (the
+            // stores are the only conditional steps), so that the lanes of a
+            // wave stay in step; running out of slots is reported after them
+            bool reused = false, full = false;
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
                 const int v = v3[i];
-                if (!((keep >> v) & 1u)) continue;
-                int u;
-                if (!reused) {
-                    u = x;
-                    reused = true;
-                } else {
-                    if (freem == 0u) return false;
-                    u = lowbit(freem);
-                    freem &= freem - 1u;
-                }
-                fresh |= 1u << u;
+                const bool kv = (keep >> v) & 1u;
+                const bool own = kv && !reused;          // first new vertex: the removed vertex's slot
+                const bool other = kv && reused;         // later ones: a free slot
+                const bool ok = !(other && freem == 0u);
+                full = full || !ok;
+                const int u = own ? x : lowbit(freem | 0x80000000u);
+                freem = other && ok ? (freem & (freem - 1u)) : freem;
+                reused = reused || kv;
+                fresh |= kv && ok ? (1u << u) : 0u;
                 S4<T> q = keep_upper ? isect3(px, pv3[i], ax, c) : isect3(pv3[i], px, ax, c);
                 q.nb = pack3<NB>(v, v, v);
-                setV(u, q);
-                if (u != x) {
+                if (kv && ok) setV(u, q);
+                if (other && ok) {
                     const uint32_t nbv = N(v);
                     setN(v, set_nbr<NB>(nbv, slot_of<NB>(nbv, x), u));
                 }
             }
+            if (full) return false;
             if (!reused) freem |= 1u << x;
         }
         // link the new vertices around the cap: from each one, walk its
