@@ -461,8 +461,8 @@ struct Poly3 {
         uint32_t todo = fresh;
         int u = lowbit(todo);
         int prev = u, cur = nbr<NB>(N(u), 0);
-        int guard = 0;
-        while (todo) {
+        // (the step bound, reported after the loop, catches a corrupted graph)
+        for (int guard = 0; todo && guard <= 4 * MAXV * MAXV; ++guard) {
             uint32_t nbc = N(cur);
             int j = slot_of<NB>(nbc, prev);
             int nxt = nbr<NB>(nbc, (j + 1) % 3);
@@ -472,14 +472,13 @@ struct Poly3 {
                 setN(u, set_nbr<NB>(N(u), 2, cur));
                 setN(cur, set_nbr<NB>(N(cur), 1, u));
                 todo &= todo - 1u;
-                if (todo) {
-                    u = lowbit(todo);
-                    prev = u;
-                    cur = nbr<NB>(N(u), 0);
-                }
+                // the next new vertex (u itself again when none is left)
+                u = todo ? lowbit(todo) : u;
+                prev = u;
+                cur = nbr<NB>(N(u), 0);
             }
-            if (++guard > 4 * MAXV * MAXV) return false;
         }
+        if (todo) return false;
         live = keep | fresh;
         return true;
     }
@@ -502,18 +501,17 @@ struct Poly3 {
         if (below == live) whole = true;
         S4<T> A = V(lowbit(live));
         if (!whole) {
-            bool found = false;
-            for (uint32_t w = below; w && !found; w &= w - 1u) {
+            // a below vertex with a neighbour at or above the plane (one
+            // exists, since below is neither empty nor every live vertex);
+            // the three neighbours are tested with selects
+            for (uint32_t w = below; w; w &= w - 1u) {
                 const int v = lowbit(w);
-                const S4<T> pv = V(v);
-                const uint32_t nbv = (uint32_t)pv.nb;
-                for (int i = 0; i < 3; ++i) {
-                    const int x = nbr<NB>(nbv, i);
-                    if (!((below >> x) & 1u)) {
-                        A = isect3(pv, V(x), ax, c);
-                        found = true;
-                        break;
-                    }
+                const uint32_t nbv = N(v);
+                const int x0 = nbr<NB>(nbv, 0), x1 = nbr<NB>(nbv, 1), x2 = nbr<NB>(nbv, 2);
+                const bool o0 = !((below >> x0) & 1u), o1 = !((below >> x1) & 1u), o2 = !((below >> x2) & 1u);
+                if (o0 || o1 || o2) {
+                    A = isect3(V(v), V(o0 ? x0 : (o1 ? x1 : x2)), ax, c);
+                    break;
                 }
             }
         }
