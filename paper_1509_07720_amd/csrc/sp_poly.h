@@ -523,7 +523,7 @@ struct Poly3 {
         uint32_t un0 = live, un1 = live, un2 = live;
         int vs = 0, vcur = 0, pc = 0, cnt = 0;
         uint32_t ncur = 0u;
-        bool open = false, ba = false;
+        bool ba = false;
         S4<T> a;
         T e0x = 0, e0y = 0, e0z = 0, epx = 0, epy = 0, epz = 0, rf = 0, rp = 0;
         // one point of the facet polygon, if valid: the fan triangle it
@@ -551,25 +551,18 @@ struct Poly3 {
             rp = valid ? rq : rp;
             cnt += valid ? 1 : 0;
         };
+        // the first facet: from the lowest below vertex through its slot 0
+        vs = vcur = lowbit(below);
+        a = V(vcur);
+        ncur = (uint32_t)a.nb;
+        ba = true;
         const int steps = 3 * __builtin_popcount(live);
+        bool done = false;
         // (three steps per trip: the walk state rotates through registers
         // instead of being copied at every back-edge; 44.5 -> 43.2 ms on the
         // soup, 2 and 4 measured in between)
 #pragma unroll 3
-        for (int it = 0; it < steps; ++it) {
-            if (!open) {
-                const uint32_t any = (un0 | un1 | un2) & below;
-                if (any == 0u) return true;
-                const int v = lowbit(any);
-                pc = ((un0 >> v) & 1u) ? 0 : (((un1 >> v) & 1u) ? 1 : 2);
-                vs = v;
-                vcur = v;
-                cnt = 0;
-                open = true;
-                a = V(vcur);
-                ncur = (uint32_t)a.nb;
-                ba = (below >> vcur) & 1u;
-            }
+        for (int it = 0; it < steps && !done; ++it) {
             const uint32_t bit = 1u << vcur;
             un0 &= pc == 0 ? ~bit : ~0u;
             un1 &= pc == 1 ? ~bit : ~0u;
@@ -591,15 +584,29 @@ struct Poly3 {
             hi.y = ba ? b.y : a.y;
             hi.z = ba ? b.z : a.z;
             acc(isect3(lo, hi, ax, c), ba != bb);
-            open = vnext != vs;
             const int np = slot_of<NB>(nnext, vcur);
-            pc = np == 2 ? 0 : np + 1;
-            vcur = vnext;
-            a = b;
-            ncur = nnext;
-            ba = bb;
+            // A facet closes when the walk is back at its first vertex; the
+            // next one starts at the lowest below vertex with an edge not yet
+            // walked, and when there is none every facet is done.  The start
+            // is chosen with selects and its vertex read on every step (from
+            // a live slot), so that the walk carries no nested branch.
+            const bool closed = vnext == vs;
+            const uint32_t any = (un0 | un1 | un2) & below;
+            const int vn = any ? lowbit(any) : vnext;
+            const S4<T> an = V(vn);
+            done = closed && any == 0u;
+            const int pn = ((un0 >> vn) & 1u) ? 0 : (((un1 >> vn) & 1u) ? 1 : 2);
+            vs = closed ? vn : vs;
+            pc = closed ? pn : (np == 2 ? 0 : np + 1);
+            vcur = closed ? vn : vnext;
+            cnt = closed ? 0 : cnt;
+            a.x = closed ? an.x : b.x;
+            a.y = closed ? an.y : b.y;
+            a.z = closed ? an.z : b.z;
+            ncur = closed ? (uint32_t)an.nb : nnext;
+            ba = closed || bb;  // a facet starts at a below vertex
         }
-        return !open && ((un0 | un1 | un2) & below) == 0u;
+        return done;
     }
 };
 
