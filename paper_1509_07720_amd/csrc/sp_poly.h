@@ -440,10 +440,12 @@ struct Poly3 {
                 const bool other = kv && reused;         // later ones: a free slot
                 const bool ok = !(other && freem == 0u);
                 full = full || !ok;
+                // (bit 31 keeps lowbit defined when no slot is free; u is then unused)
                 const int u = own ? x : lowbit(freem | 0x80000000u);
                 freem = other && ok ? (freem & (freem - 1u)) : freem;
                 reused = reused || kv;
                 fresh |= kv && ok ? (1u << u) : 0u;
+                // (unused, and possibly not finite, when v is not kept)
                 S4<T> q = keep_upper ? isect3(px, pv3[i], ax, c) : isect3(pv3[i], px, ax, c);
                 q.nb = pack3<NB>(v, v, v);
                 if (kv && ok) setV(u, q);
