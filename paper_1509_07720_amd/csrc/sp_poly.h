@@ -498,10 +498,12 @@ struct Poly3 {
         s24 = T(0);
         uint32_t below = whole ? live : below_mask(ax, c);
         if (below_out) *below_out = below;
-        if (live == 0u) return true;
-        if (below == 0u) return true;
+        // nothing below (below is part of live, so also no polytope): the
+        // walk below takes no step and the sums stay zero; the slot indices
+        // read meanwhile stay valid
+        const bool none = below == 0u;
         if (below == live) whole = true;
-        S4<T> A = V(lowbit(live));
+        S4<T> A = V(live ? lowbit(live) : 0);
         if (!whole) {
             // a below vertex with a neighbour at or above the plane (one
             // exists, since below is neither empty nor every live vertex);
@@ -554,11 +556,11 @@ struct Poly3 {
             cnt += valid ? 1 : 0;
         };
         // the first facet: from the lowest below vertex through its slot 0
-        vs = vcur = lowbit(below);
+        vs = vcur = none ? 0 : lowbit(below);
         a = V(vcur);
         ncur = (uint32_t)a.nb;
         ba = true;
-        const int steps = 3 * __builtin_popcount(live);
+        const int steps = none ? 0 : 3 * __builtin_popcount(live);
         bool done = false;
         // (three steps per trip: the walk state rotates through registers
         // instead of being copied at every back-edge; 44.5 -> 43.2 ms on the
@@ -608,7 +610,7 @@ struct Poly3 {
             ncur = closed ? (uint32_t)an.nb : nnext;
             ba = closed || bb;  // a facet starts at a below vertex
         }
-        return done;
+        return done || none;
     }
 };
 
